@@ -1,0 +1,162 @@
+/*
+ * oracle.h -- plain, slow FP64 CPU oracle for the batched shifted-rotated
+ * evaluation and the DE / PSO / SHADE generation steps.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this code; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the GPU path: the
+ * Philox generator, the instance generator, the six objective functions and
+ * the algorithm steps are written here a second time, from their published
+ * definitions, in double precision, with no blocking or fusion.
+ *
+ * Layout: populations are individual-major, x[i*dim + j] (the obvious CPU
+ * layout).  Matrices are row-major.  All floating point is double; the
+ * library is compiled with -O2 -ffp-contract=off and no fast-math.
+ *
+ * Parity pins (see tests/test_oracle_*.py): Philox known-answer vectors;
+ * orthogonality, det and LAPACK-QR uniqueness of the rotation; f(o) = f*
+ * exactly; textbook closed forms at M = I, o = 0; high-precision textbook
+ * definitions at random points; D = 2 brute-force grid minima; exhaustive
+ * donor enumeration; DE/PSO/SHADE invariants; resume bit-identity.
+ */
+#ifndef SEVO_ORACLE_H
+#define SEVO_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Function identifiers (same numbering as the product ABI, by definition). */
+enum { ORC_ELLIPSOID = 0, ORC_ROSENBROCK = 1, ORC_RASTRIGIN = 2,
+       ORC_SCHWEFEL = 3, ORC_GRIEWANK = 4, ORC_ACKLEY = 5, ORC_NFUNC = 6 };
+enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2 };
+
+/* Philox stream tags (third counter word, bits 24..31). */
+enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
+       ORC_TAG_PSO_R = 4, ORC_TAG_SHADE_P = 5, ORC_TAG_SHADE_C = 6,
+       ORC_TAG_SHADE_D = 7, ORC_TAG_SHIFT_O = 16, ORC_TAG_ROT_N = 17 };
+
+typedef struct {
+    int32_t func;
+    int32_t dim;
+    double lb, ub;
+} orc_problem;
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Uniform and integer maps of 32-bit words. */
+double   orc_u24(uint32_t w);                 /* (w >> 8) * 2^-24, in [0, 1)      */
+double   orc_u53(uint32_t a, uint32_t b);     /* 53-bit uniform in [0, 1)         */
+uint32_t orc_range(uint32_t w, uint32_t n);   /* floor(w * n / 2^32), in [0, n)   */
+uint32_t orc_cr_threshold(double cr);         /* ceil(cr * 2^24), clamped to [0, 2^24] */
+
+/* Instance (o, M) of (func, dim, instance); G (optional) receives the
+ * Gaussian matrix before orthogonalisation.  Returns 0 or -1. */
+int orc_instance(int32_t func, int32_t dim, uint32_t instance, uint64_t inst_seed,
+                 double *o, double *M, double *G);
+
+/* Householder QR of the n x n row-major matrix A; Q gets the orthogonal
+ * factor with every diagonal entry of R made positive. */
+int orc_householder_q(int32_t n, const double *A, double *Q);
+
+/* Error e = f(x) - f* for one point, and for n points stored as
+ * single-precision structure-of-arrays X[j*ld + i] (the GPU state type),
+ * widened exactly. */
+double orc_error(int32_t func, int32_t dim, const double *o, const double *M, const double *x);
+void   orc_error_soa_f32(int32_t func, int32_t dim, const double *o, const double *M,
+                         const float *X, int64_t ld, int32_t n, double *e);
+void   orc_error_aos(int32_t func, int32_t dim, const double *o, const double *M,
+                     const double *X, int32_t n, double *e);
+/* Error as a function of the rotated vector z (M and o already applied). */
+double orc_error_z(int32_t func, int32_t dim, const double *z);
+
+/* ---- Differential evolution, rand/1/bin with midpoint-target repair ---- */
+/* Population initialisation (generation 0): X[i*dim + j] = lb + (ub-lb) u24. */
+void orc_init_population(const orc_problem *pb, int32_t np, uint32_t run_uid,
+                         uint64_t seed, double *X);
+
+/* Donor indices (r1, r2, r3) and jrand from four raw words: r1 uniform over
+ * the NP-1 indices other than i, r2 over the NP-2 others left, r3 over the
+ * NP-3 left, each drawn once and stepped past the excluded indices. */
+void orc_donors_from_words(int32_t np, int32_t dim, int32_t i, const uint32_t w[4],
+                           int32_t out[4]);
+/* Donor indices and jrand for individual i of generation t (rand/1). */
+void orc_de_donors(int32_t np, int32_t dim, int32_t i, uint32_t run_uid, uint64_t seed,
+                   uint32_t t, int32_t out[4]);
+
+/* One synchronous generation.  Inputs X, eX; outputs trial U, eU and the
+ * next population Xn, eXn (Xn may alias nothing).  Optional outputs
+ * (NULL to skip): donors[i*4 + k], mask[i*dim + j], replaced[i]. */
+int orc_de_generation(const orc_problem *pb, const double *o, const double *M,
+                      int32_t np, double F, double CR, uint32_t run_uid, uint64_t seed,
+                      uint32_t t, const double *X, const double *eX,
+                      double *U, double *eU, double *Xn, double *eXn,
+                      int32_t *donors, uint8_t *mask, uint8_t *replaced);
+
+/* ---- PSO, inertia weight, global-best topology ---- */
+int orc_pso_init(const orc_problem *pb, const double *o, const double *M, int32_t np,
+                 uint32_t run_uid, uint64_t seed, double *X, double *V, double *P,
+                 double *eX, double *eP, int32_t *g);
+int orc_pso_iteration(const orc_problem *pb, const double *o, const double *M, int32_t np,
+                      double w, double c1, double c2, double vmax,
+                      uint32_t run_uid, uint64_t seed, uint32_t t,
+                      double *X, double *V, double *P, double *eX, double *eP, int32_t *g);
+
+/* ---- SHADE (success-history adaptation, current-to-pbest/1, no archive) ---- */
+/* Per-individual draws: idx[i*6 + k] = (memory slot, pbest index, r1, r2,
+ * jrand, Cauchy retries); F[i], CR[i]; sorted[] = ranking used for pbest;
+ * margin[i*2 + 0] = smallest |F candidate| seen (distance of the F > 0
+ * decisions from their threshold), margin[i*2 + 1] = smallest distance, in
+ * units of 2^-24, between a crossover uniform and CR (jrand excluded).  All
+ * optional outputs may be NULL. */
+int orc_shade_generation(const orc_problem *pb, const double *o, const double *M,
+                         int32_t np, double p, int32_t H, double *MF, double *MCR,
+                         int32_t *pos, uint32_t run_uid, uint64_t seed, uint32_t t,
+                         const double *X, const double *eX,
+                         double *U, double *eU, double *Xn, double *eXn,
+                         int32_t *idx, double *F, double *CR, double *margin,
+                         uint8_t *mask, uint8_t *replaced, int32_t *sorted);
+/* Memory update from the successful set (F, CR, improvement delta). */
+void orc_shade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos,
+                             int32_t n_s, const double *SF, const double *SCR,
+                             const double *dS);
+int32_t orc_shade_pnum(double p, int32_t np);
+
+/* ---- Whole-run driver with FE accounting and the 200-FE recorder ---- */
+typedef struct {
+    int32_t algo;
+    int32_t func, dim;
+    double lb, ub;
+    uint32_t instance;
+    uint32_t run_uid;
+    int32_t np;
+    int64_t budget;        /* function evaluations */
+    double F, CR;          /* DE */
+    double w, c1, c2, vmax;/* PSO */
+    double p;              /* SHADE: pbest fraction */
+    int32_t H;             /* SHADE: memory size */
+} orc_run_desc;
+
+typedef struct {
+    double best_e;         /* best error over the first `budget` evaluations */
+    int64_t fes;           /* evaluations performed (whole generations) */
+    int32_t generations;   /* generations after initialisation */
+    int32_t success;       /* best_e <= 1e-8 */
+} orc_run_result;
+
+#define ORC_TRACE_EVERY 200
+int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
+            orc_run_result *res, double *trace, int64_t trace_len, double *best_x);
+
+/* Constants of the Schwefel form (the argmax s and c = s sin sqrt s). */
+double orc_schwefel_s(void);
+double orc_schwefel_c(void);
+double orc_schwefel_lambda(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,314 @@
+"""Pins of the oracle's DE, PSO and SHADE generation steps and its run driver.
+
+Each check follows from the algorithm's definition rather than from the
+oracle's code: special parameter values that collapse a step to something
+known (F = 0, CR in {0, 1}, c1 = c2 = 0), invariants (bounds, monotone best,
+distinct donors), the SHADE memory update on a hand-built success set,
+distribution tests of the sampled F and CR, and the recorder's FE accounting
+recomputed from the step outputs.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+
+SEED = 250517430
+ISEED = 250517431
+LB, UB = -100.0, 100.0
+
+
+def _pop(func, dim, np_, run_uid=3):
+    o, M = O.instance(func, dim, 0, ISEED)
+    X = O.init_population(func, dim, LB, UB, np_, run_uid, SEED)
+    eX = O.errors(func, o, M, X)
+    return o, M, X, eX
+
+
+def test_init_population_in_bounds_and_on_float32_grid():
+    X = O.init_population(O.RASTRIGIN, 10, LB, UB, 50, 0, SEED)
+    assert X.min() >= LB and X.max() < UB
+    # lb + 200 u24 is exact in double; its float32 rounding is what the GPU stores
+    assert stats.kstest(((X - LB) / (UB - LB)).ravel(), "uniform").pvalue > 1e-3
+    Y = O.init_population(O.RASTRIGIN, 10, LB, UB, 50, 1, SEED)
+    assert not np.array_equal(X, Y)
+
+
+def test_de_f0_cr1_copies_r1():
+    o, M, X, eX = _pop(O.RASTRIGIN, 10, 20)
+    out = O.de_generation(O.RASTRIGIN, LB, UB, o, M, X, eX, 0.0, 1.0, 3, SEED, 1)
+    for i in range(20):
+        assert np.array_equal(out["U"][i], X[out["donors"][i, 0]])
+        assert out["mask"][i].all()
+
+
+def test_de_cr0_changes_exactly_jrand():
+    o, M, X, eX = _pop(O.ELLIPSOID, 10, 20)
+    out = O.de_generation(O.ELLIPSOID, LB, UB, o, M, X, eX, 0.5, 0.0, 3, SEED, 1)
+    for i in range(20):
+        jr = out["donors"][i, 3]
+        assert out["mask"][i].sum() == 1 and out["mask"][i, jr]
+        diff = np.nonzero(out["U"][i] != X[i])[0]
+        assert set(diff) <= {jr}
+        r1, r2, r3 = out["donors"][i, :3]
+        v = X[r1, jr] + 0.5 * (X[r2, jr] - X[r3, jr])
+        want = v if LB <= v <= UB else (0.5 * (LB + X[i, jr]) if v < LB else 0.5 * (UB + X[i, jr]))
+        assert out["U"][i, jr] == want
+
+
+def test_de_mutation_crossover_repair_definition():
+    o, M, X, eX = _pop(O.SCHWEFEL, 7, 30)
+    F, CR = 0.9, 0.5
+    out = O.de_generation(O.SCHWEFEL, LB, UB, o, M, X, eX, F, CR, 3, SEED, 4)
+    U, mask = out["U"], out["mask"]
+    assert U.min() >= LB and U.max() <= UB
+    n_repaired = 0
+    for i in range(30):
+        r1, r2, r3, jr = out["donors"][i]
+        assert len({i, r1, r2, r3}) == 4
+        v = X[r1] + F * (X[r2] - X[r3])
+        for j in range(7):
+            if not mask[i, j]:
+                assert U[i, j] == X[i, j]
+            elif v[j] < LB:
+                assert U[i, j] == 0.5 * (LB + X[i, j]); n_repaired += 1
+            elif v[j] > UB:
+                assert U[i, j] == 0.5 * (UB + X[i, j]); n_repaired += 1
+            else:
+                assert U[i, j] == v[j]
+    assert n_repaired > 0
+    # mask frequency ~ CR outside jrand
+    assert abs(mask.mean() - (CR + (1 - CR) / 7)) < 0.1
+
+
+def test_de_selection_greedy_ties_to_trial():
+    o, M, X, eX = _pop(O.ACKLEY, 5, 12)
+    out = O.de_generation(O.ACKLEY, LB, UB, o, M, X, eX, 0.5, 0.9, 3, SEED, 2)
+    assert np.array_equal(out["replaced"], out["eU"] <= eX)
+    assert np.all(out["eX"] <= eX)
+    # identical population: every trial equals its target, every tie goes to the trial
+    Xs = np.tile(X[:1], (12, 1))
+    eXs = O.errors(O.ACKLEY, o, M, Xs)
+    out = O.de_generation(O.ACKLEY, LB, UB, o, M, Xs, eXs, 0.5, 0.9, 3, SEED, 2)
+    assert np.array_equal(out["U"], Xs) and np.array_equal(out["eU"], eXs)
+    assert out["replaced"].all()
+
+
+def test_de_nan_counts_as_infinity():
+    o, M, X, eX = _pop(O.RASTRIGIN, 4, 8)
+    eX = eX.copy()
+    eX[2] = np.nan
+    out = O.de_generation(O.RASTRIGIN, LB, UB, o, M, X, eX, 0.5, 0.9, 3, SEED, 2)
+    assert out["replaced"][2]
+
+
+def test_de_steps_depend_only_on_generation_counter():
+    # resume bit-identity: generation t's draws do not depend on history
+    o, M, X, eX = _pop(O.GRIEWANK, 6, 10)
+    a = O.de_generation(O.GRIEWANK, LB, UB, o, M, X, eX, 0.5, 0.9, 3, SEED, 9)
+    O.de_generation(O.GRIEWANK, LB, UB, o, M, X, eX, 0.5, 0.9, 3, SEED, 2)
+    b = O.de_generation(O.GRIEWANK, LB, UB, o, M, X, eX, 0.5, 0.9, 3, SEED, 9)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+# ------------------------------------------------------------------ PSO
+
+def test_pso_init():
+    o, M = O.instance(O.ELLIPSOID, 8, 0, ISEED)
+    st = O.pso_init(O.ELLIPSOID, LB, UB, o, M, 16, 5, SEED)
+    assert np.all(st["V"] == 0) and np.array_equal(st["P"], st["X"])
+    assert st["g"] == int(np.argmin(st["eP"]))
+
+
+def test_pso_inertia_only_decay():
+    # c1 = c2 = 0: v_t = w^t v_0 while no clamp or bound is hit
+    o, M = O.instance(O.ELLIPSOID, 6, 0, ISEED)
+    st = O.pso_init(O.ELLIPSOID, LB, UB, o, M, 8, 5, SEED)
+    st["X"] = np.zeros_like(st["X"])
+    v0 = np.random.default_rng(0).uniform(-1, 1, st["V"].shape)
+    st["V"] = v0.copy()
+    w = 0.7298
+    x_expect = np.zeros_like(v0)
+    for t in range(1, 6):
+        st = O.pso_iteration(O.ELLIPSOID, LB, UB, o, M, st, w, 0.0, 0.0, 40.0, 5, SEED, t)
+        x_expect = x_expect + w ** t * v0
+        assert np.allclose(st["V"], w ** t * v0, rtol=1e-14, atol=0)
+        assert np.allclose(st["X"], x_expect, rtol=1e-13, atol=1e-15)
+
+
+def test_pso_invariants():
+    func = O.RASTRIGIN
+    o, M = O.instance(func, 10, 0, ISEED)
+    st = O.pso_init(func, LB, UB, o, M, 40, 9, SEED)
+    prev = st["eP"].copy()
+    hit_clamp = hit_bound = False
+    for t in range(1, 30):
+        st = O.pso_iteration(func, LB, UB, o, M, st, 0.7298, 1.49618, 1.49618, 40.0, 9, SEED, t)
+        assert np.all(np.abs(st["V"]) <= 40.0)
+        assert st["X"].min() >= LB and st["X"].max() <= UB
+        assert np.all(st["eP"] <= prev)
+        improved = st["eP"] < prev
+        # personal bests move only on strict improvement, to the current position
+        assert np.array_equal(st["P"][improved], st["X"][improved])
+        assert st["g"] == int(np.argmin(st["eP"]))
+        hit_clamp |= bool(np.any(np.abs(st["V"]) == 40.0))
+        hit_bound |= bool(np.any((st["X"] == LB) | (st["X"] == UB)))
+        prev = st["eP"].copy()
+    assert hit_clamp and hit_bound
+
+
+def test_pso_gbest_ties_lowest_index():
+    o, M = O.instance(O.ELLIPSOID, 4, 0, ISEED)
+    st = O.pso_init(O.ELLIPSOID, LB, UB, o, M, 6, 2, SEED)
+    # recorded personal bests far below any true error: no particle improves,
+    # and the tie among indices 1, 3, 4 must resolve to 1
+    st["eP"] = np.array([5e-9, 1e-9, 3e-9, 1e-9, 1e-9, 7e-9])
+    st2 = O.pso_iteration(O.ELLIPSOID, LB, UB, o, M, st, 0.7298, 1.49618, 1.49618, 40.0, 2, SEED, 1)
+    assert np.array_equal(st2["eP"], st["eP"])
+    assert st2["g"] == 1
+
+
+# ------------------------------------------------------------------ SHADE
+
+def test_shade_memory_update_closed_form():
+    MF = np.full(6, 0.5); MCR = np.full(6, 0.5)
+    MF2, MCR2, pos = O.shade_memory_update(MF, MCR, 5, [0.5, 1.0], [0.2, 0.6], [1.0, 3.0])
+    # weights 1/4, 3/4: M_CR = 0.25*0.2 + 0.75*0.6, M_F = Lehmer mean sum(w F^2)/sum(w F)
+    assert MCR2[5] == pytest.approx(0.5, abs=1e-15)
+    assert MF2[5] == pytest.approx((0.25 * 0.25 + 0.75 * 1.0) / (0.25 * 0.5 + 0.75 * 1.0), rel=1e-15)
+    assert pos == 0
+    assert np.array_equal(MF2[:5], MF[:5])
+    # empty success set: nothing changes
+    MF3, MCR3, pos3 = O.shade_memory_update(MF, MCR, 2, [], [], [])
+    assert np.array_equal(MF3, MF) and pos3 == 2
+
+
+@pytest.mark.parametrize("np_,want", [(180, 18), (200, 20), (10, 2), (4, 2), (25, 3), (35, 4)])
+def test_shade_pnum(np_, want):
+    assert O.shade_pnum(0.1, np_) == want
+
+
+def test_shade_generation_invariants():
+    func, D, np_ = O.ROSENBROCK, 10, 180
+    o, M, X, eX = _pop(func, D, np_)
+    MF = np.full(6, 0.5); MCR = np.full(6, 0.5)
+    out = O.shade_generation(func, LB, UB, o, M, X, eX, MF, MCR, 0, 0.1, 3, SEED, 1)
+    idx = out["idx"]
+    order = np.lexsort((np.arange(np_), eX))
+    assert np.array_equal(out["sorted"], order)
+    top = set(order[:18].tolist())
+    for i in range(np_):
+        k, pb, r1, r2, jr, retries = idx[i]
+        assert 0 <= k < 6 and pb in top
+        assert r1 != i and r2 not in (i, r1) and 0 <= jr < D
+        assert 0 < out["F"][i] <= 1 and 0 <= out["CR"][i] <= 1
+        v = X[i] + out["F"][i] * (X[pb] - X[i]) + out["F"][i] * (X[r1] - X[r2])
+        for j in range(D):
+            if not out["mask"][i, j]:
+                assert out["U"][i, j] == X[i, j]
+            elif LB <= v[j] <= UB:
+                assert out["U"][i, j] == v[j]
+    assert out["pos"] == 1
+    succ = out["eU"] < eX
+    if succ.any():
+        d = (eX - out["eU"])[succ]
+        w = d / d.sum()
+        assert out["MCR"][0] == pytest.approx(float(np.sum(w * out["CR"][succ])), rel=1e-12)
+        F = out["F"][succ]
+        assert out["MF"][0] == pytest.approx(float(np.sum(w * F * F) / np.sum(w * F)), rel=1e-12)
+
+
+def test_shade_parameter_distributions():
+    # F ~ Cauchy(0.5, 0.1) redrawn while <= 0 then capped at 1; CR ~ N(0.5, 0.1) clipped
+    func, D, np_ = O.ELLIPSOID, 4, 200
+    o, M, X, eX = _pop(func, D, np_)
+    MF = np.full(6, 0.5); MCR = np.full(6, 0.5)
+    Fs, CRs = [], []
+    for t in range(1, 31):
+        out = O.shade_generation(func, LB, UB, o, M, X, eX, MF, MCR, 0, 0.1, 3, SEED, t)
+        Fs.append(out["F"]); CRs.append(out["CR"])
+    F = np.concatenate(Fs); CR = np.concatenate(CRs)
+    c = stats.cauchy(0.5, 0.1)
+    p0 = c.cdf(0.0)
+
+    def cdf_f(x):
+        x = np.asarray(x, dtype=float)
+        return np.where(x >= 1.0, 1.0, (c.cdf(x) - p0) / (1 - p0))
+    # compare below the cap (the cap has a point mass at 1)
+    below = F[F < 1.0]
+    cond = lambda x: cdf_f(x) / cdf_f(np.nextafter(1.0, 0))
+    assert stats.kstest(below, cond).pvalue > 1e-3
+    assert abs(np.mean(F == 1.0) - (1 - cdf_f(np.nextafter(1.0, 0)))) < 0.01
+    n = stats.norm(0.5, 0.1)
+    inner = CR[(CR > 0) & (CR < 1)]
+    assert stats.kstest(inner, lambda x: (n.cdf(x) - n.cdf(0)) / (n.cdf(1) - n.cdf(0))).pvalue > 1e-3
+
+
+# ------------------------------------------------------------------ run driver
+
+def _desc(algo, func, dim, np_, budget, **kw):
+    d = dict(algo=algo, func=func, dim=dim, lb=LB, ub=UB, instance=0, run_uid=1, np=np_,
+             budget=budget, F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618,
+             vmax=0.2 * (UB - LB), p=0.1, H=6)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("algo", [O.ALGO_DE, O.ALGO_PSO, O.ALGO_SHADE])
+def test_run_matches_steps_and_recorder(algo):
+    func, D, np_, budget = O.RASTRIGIN, 5, 20, 1000
+    d = _desc(algo, func, D, np_, budget)
+    res, trace, best_x = O.run(d, SEED, ISEED, trace_len=budget // 200)
+    # replay with the step functions and recompute the recorder in Python
+    o, M = O.instance(func, D, 0, ISEED)
+    evals = []
+    if algo == O.ALGO_PSO:
+        st = O.pso_init(func, LB, UB, o, M, np_, 1, SEED)
+        evals += list(zip(st["eX"], st["X"]))
+        t = 0
+        while len(evals) < budget:
+            t += 1
+            st = O.pso_iteration(func, LB, UB, o, M, st, 0.7298, 1.49618, 1.49618, 40.0, 1, SEED, t)
+            evals += list(zip(st["eX"], st["X"]))
+    else:
+        X = O.init_population(func, D, LB, UB, np_, 1, SEED)
+        eX = O.errors(func, o, M, X)
+        evals += list(zip(eX, X))
+        MF = np.full(6, 0.5); MCR = np.full(6, 0.5); pos = 0
+        t = 0
+        while len(evals) < budget:
+            t += 1
+            if algo == O.ALGO_DE:
+                out = O.de_generation(func, LB, UB, o, M, X, eX, 0.5, 0.9, 1, SEED, t)
+            else:
+                out = O.shade_generation(func, LB, UB, o, M, X, eX, MF, MCR, pos, 0.1, 1, SEED, t)
+                MF, MCR, pos = out["MF"], out["MCR"], out["pos"]
+            evals += list(zip(out["eU"], out["U"]))
+            X, eX = out["X"], out["eX"]
+    e = np.array([v for v, _ in evals])
+    assert res["fes"] == len(e) and res["generations"] == t
+    assert res["best_e"] == e[:budget].min()
+    assert np.array_equal(best_x, evals[int(np.argmin(e[:budget]))][1])
+    want_trace = [e[: 200 * (k + 1)].min() for k in range(budget // 200)]
+    assert np.array_equal(trace, want_trace)
+    assert np.all(np.diff(trace) <= 0)
+
+
+def test_run_fe_accounting_shade_c4_shape():
+    # D = 10, NP = 180, budget 10000 D: 555 generations, last one overshoots to 100080 FEs
+    d = _desc(O.ALGO_SHADE, O.ELLIPSOID, 10, 180, 100000)
+    res, trace, _ = O.run(d, SEED, ISEED, trace_len=500)
+    assert res["generations"] == 555 and res["fes"] == 100080
+    assert np.all(np.isfinite(trace)) and np.all(np.diff(trace) <= 0)
+
+
+def test_run_c1_de_converges():
+    # the plain DE configuration: Rastrigin, D = 10, NP = 50, 1000 generations
+    d = _desc(O.ALGO_DE, O.RASTRIGIN, 10, 50, 50 * 1001)
+    res, trace, _ = O.run(d, SEED, ISEED, trace_len=50 * 1001 // 200)
+    assert res["generations"] == 1000 and res["fes"] == 50050
+    assert res["best_e"] < trace[0]
+    assert res["success"] == (res["best_e"] <= 1e-8)
