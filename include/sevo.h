@@ -1,0 +1,267 @@
+/*
+ * sevo.h -- C ABI of the MI355X (gfx950) batched shifted-rotated evaluation
+ * and DE / PSO / SHADE generation library.
+ *
+ * What the calls compute is the method of "SEvoBench: A C++ Framework For
+ * Evolutionary Single-Objective Optimization Benchmarking" (arXiv 2505.17430):
+ *   - sevo_evaluate / sevo_evaluate_batch: the fitness evaluation that the
+ *     Problem module provides to every algorithm (Sec. 2.3), here for
+ *     randomly shifted and rotated instances of six continuous test
+ *     functions, many problems / instances / populations per call (the
+ *     multiple random instances per problem of Sec. 1 and Sec. 2.3; the
+ *     transformed solution vector of Sec. 3.2);
+ *   - sevo_de_step: one generation of the DE module (Sec. 2.2, Listing 1's
+ *     binomial crossover and midpoint-target repair) with rand/1 mutation and
+ *     greedy one-to-one selection;
+ *   - sevo_pso_step: one iteration of the PSO module (Sec. 2.2) with the
+ *     inertia-weight update and global-best topology;
+ *   - sevo_run: the Experiment module's independent runs (Sec. 2.4, Listing
+ *     3's evo_bench) for DE, PSO and SHADE (Listing 1) at once, each with a
+ *     function-evaluation budget (Listing 4's loop) and the best-so-far
+ *     record every 200 evaluations (Sec. 2.4, Sec. 3.2).
+ *
+ * Conventions shared by every call
+ *   - Status: every call returns SEVO_OK (0) or a negative SEVO_E* code and
+ *     never throws or aborts; sevo_last_error(ctx) returns the message of the
+ *     last failure on that context.
+ *   - Pointers: "device" pointers are HIP device memory on the context's GPU
+ *     (for example torch tensors' data_ptr), "host" pointers are CPU memory.
+ *     The caller owns every buffer it passes and keeps it alive until the
+ *     work on `stream` has finished.  Descriptor structs are read during the
+ *     call only.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *     are asynchronous on that stream unless stated otherwise; device faults
+ *     surface as SEVO_EDEVICE from a later call or from sevo_sync.
+ *   - Layout: populations are structure-of-arrays.  Coordinate d of point i
+ *     is at x[d * ld + i] (the point index is the fast one, so a wavefront
+ *     reads consecutive points of one coordinate).  Batched runs add a run
+ *     stride: x[r * run_stride + d * ld + i].
+ *   - Values: device fitness is the error e = f(x) - f*, never f itself, so
+ *     single precision keeps its resolution near the optimum.
+ *   - Threads: a context is not thread-safe; use one per host thread.
+ */
+#ifndef SEVO_H
+#define SEVO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define SEVO_OK            0
+#define SEVO_EINVAL       -1   /* bad argument: null pointer, size, enum, bounds   */
+#define SEVO_ENOMEM       -2   /* host or device allocation failed                 */
+#define SEVO_EDEVICE      -3   /* HIP runtime error (message carries its string)   */
+#define SEVO_EUNSUPPORTED -4   /* valid request this build does not implement      */
+#define SEVO_ESTATE       -5   /* call out of order (e.g. step before init)        */
+
+/* ---- test functions: e(x) = f(x) - f*, z = M (x - o), indices 1..D ----
+ * ELLIPSOID   sum 10^(6(i-1)/(D-1)) z_i^2                       (condition 1e6)
+ * ROSENBROCK  sum_{i<D} 100 (w_i^2 - w_{i+1})^2 + (w_i - 1)^2,  w = z + 1
+ * RASTRIGIN   sum z_i^2 - 10 cos(2 pi z_i) + 10
+ * SCHWEFEL    sum g(z_i + s), g(u) = c - u sin(sqrt|u|) for |u| <= 500,
+ *             g(u) = g(+-500) + 0.01 (|u| - 500)^2 beyond; s = 420.968746...,
+ *             c = s sin(sqrt s) = 418.98288727... so that g(s) = 0
+ * GRIEWANK    1 + sum z_i^2 / 4000 - prod cos(z_i / sqrt(i))
+ * ACKLEY      -20 exp(-0.2 sqrt(sum z^2 / D)) - exp(sum cos(2 pi z) / D) + 20 + e
+ */
+enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFEL = 3,
+       SEVO_GRIEWANK = 4, SEVO_ACKLEY = 5 };
+
+/* Arithmetic of the evaluation.  FP32: FP64 shift, FP32 rotation on matrix
+ * cores, compensated FP32 reduction; state and errors are float.
+ * SPLIT_BF16: as FP32 but the rotation is three bf16 products (hi*hi +
+ * hi*lo + lo*hi) with FP32 accumulation.  FP64: everything in double;
+ * state and errors are double. */
+enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
+
+enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2 };
+
+typedef struct sevo_ctx sevo_ctx;   /* opaque, library-owned */
+
+/* A problem: function, dimension, box [lb, ub]^D and optimum value f*.
+ * (problem, instance) determines (o, M) deterministically from the
+ * context's instance seed. */
+typedef struct {
+    int32_t func;
+    int32_t dim;       /* 2 .. 1024 */
+    double lb, ub;     /* lb < ub; populations live in [lb, ub]^dim */
+    double f_star;     /* added only on output in double; 100 in the workloads */
+} sevo_problem;
+
+/* ---- context ---- */
+
+/* Create a context on HIP device `hip_device`.  `base_seed` keys every
+ * algorithm draw (Philox key word 1, low and high 32 bits xor-folded);
+ * `instance_seed` keys the instance generator.  *out receives the context. */
+int sevo_create(sevo_ctx **out, int32_t hip_device, uint64_t base_seed, uint64_t instance_seed);
+
+/* Destroy the context and free everything it owns (instance cache, internal
+ * workspaces).  Waits for the context's outstanding work. */
+int sevo_destroy(sevo_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Valid until the next
+ * call on ctx.  Accepts NULL (then describes the last sevo_create failure). */
+const char *sevo_last_error(const sevo_ctx *ctx);
+
+/* Block until all work queued by this library on `stream` has finished and
+ * report any asynchronous device error as SEVO_EDEVICE. */
+int sevo_sync(sevo_ctx *ctx, void *stream);
+
+/* ---- instances ---- */
+
+/* Copy the instance (o, M) of (problem, instance) to host buffers
+ * o_host[dim] and M_host[dim*dim] (row-major; z = M (x - o)).  Either may
+ * be NULL.  The instance is generated on first use: o_j = -80 + 160 u,
+ * u a 53-bit Philox uniform; M = Q of the Householder QR of a Philox /
+ * Box-Muller N(0,1) matrix with diag(R) > 0.  Synchronous. */
+int sevo_instance(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
+                  double *o_host, double *M_host);
+
+/* The same instance computed on the host only, without a context or a GPU
+ * (for callers that evaluate elsewhere).  Synchronous; o_host[dim],
+ * M_host[dim*dim] are required. */
+int sevo_generate_instance(int32_t func, int32_t dim, uint32_t instance, uint64_t instance_seed,
+                           double *o_host, double *M_host);
+
+/* Register a user-defined instance for (problem, instance), replacing the
+ * generated one (a user-defined problem, Sec. 2.3): o_host[dim] and
+ * M_host[dim*dim] are copied; M need not be orthogonal.  Synchronous. */
+int sevo_set_instance(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
+                      const double *o_host, const double *M_host);
+
+/* ---- evaluation ---- */
+
+/* Errors of n points of one (problem, instance).
+ *   x       device, [dim][ld] structure-of-arrays, float (FP32, SPLIT_BF16)
+ *           or double (FP64); ld >= n.
+ *   err_out device, [n], float or double like x: e = f(x) - f*.
+ * n = 0 is a no-op.  Asynchronous on `stream`. */
+int sevo_evaluate(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
+                  const void *x, int64_t ld, int32_t n, void *err_out,
+                  int32_t precision, void *stream);
+
+/* Many (problem, instance, population) items in one launch sequence.  Items
+ * may mix functions, dimensions and instances; each item is evaluated as by
+ * sevo_evaluate.  `items` is a host array read during the call. */
+typedef struct {
+    sevo_problem prob;
+    uint32_t instance;
+    int32_t n;
+    int64_t ld;
+    const void *x;        /* device */
+    void *err_out;        /* device */
+} sevo_eval_item;
+
+int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
+                        int32_t precision, void *stream);
+
+/* ---- one generation at a time ---- */
+
+/* State of `n_runs` runs of one (problem, instance): run r uses Philox key
+ * run_uid0 + r.  All buffers are device memory of the precision's type
+ * (float for FP32 / SPLIT_BF16, double for FP64), laid out as
+ * buf[r * run_stride + d * ld + i] for populations and buf[r * ld + i] for
+ * per-individual values.  `generation` is the counter t of the step being
+ * made: 0 initialises (x uniform in the box, evaluated), t >= 1 makes
+ * generation t from generation t - 1. */
+typedef struct {
+    int32_t n_runs;
+    int32_t np;            /* population size, >= 4 */
+    int64_t ld;            /* >= np */
+    int64_t run_stride;    /* >= dim * ld */
+    uint32_t run_uid0;
+    uint32_t generation;
+    void *x;               /* in/out population                              */
+    void *ex;              /* in/out errors of x                             */
+    void *u;               /* out: trial vectors of this generation          */
+    void *eu;              /* out: errors of the trials                      */
+    int32_t *donors;       /* optional out, [r][4][ld]: r1, r2, r3, jrand     */
+    uint8_t *replaced;     /* optional out, [r][ld]: 1 where the trial won    */
+} sevo_de_state;
+
+typedef struct {
+    double F;              /* scale factor */
+    double CR;             /* crossover rate; mask bit j is u_j < CR or j = jrand */
+} sevo_de_params;
+
+/* One DE rand/1/bin generation (t >= 1): donors r1, r2, r3 distinct and
+ * != i, v = x_r1 + F (x_r2 - x_r3), binomial crossover with a forced jrand
+ * coordinate, out-of-box coordinates repaired to the midpoint between the
+ * bound and the parent coordinate, trials evaluated, then every trial
+ * replaces its parent when e(u) <= e(x) (NaN counts as +infinity).
+ * generation = 0 initialises x and ex instead.  Asynchronous. */
+int sevo_de_step(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
+                 const sevo_de_state *st, const sevo_de_params *par,
+                 int32_t precision, void *stream);
+
+typedef struct {
+    int32_t n_runs;
+    int32_t np;            /* swarm size, >= 1 */
+    int64_t ld;
+    int64_t run_stride;
+    uint32_t run_uid0;
+    uint32_t iteration;    /* 0 initialises; t >= 1 makes iteration t */
+    void *x, *v, *p;       /* in/out positions, velocities, personal bests   */
+    void *ex, *ep;         /* out errors of x; in/out errors of p             */
+    int32_t *gbest;        /* in/out, device [n_runs]: index of the best p    */
+} sevo_pso_state;
+
+typedef struct {
+    double w, c1, c2;      /* inertia, cognitive and social weights */
+    double vmax;           /* |v_j| <= vmax */
+} sevo_pso_params;
+
+/* One synchronous PSO iteration (t >= 1): per coordinate
+ * v = w v + c1 r1 (p - x) + c2 r2 (g - x) with r1, r2 uniform draws,
+ * |v| clamped to vmax, x += v, a coordinate leaving the box is put on the
+ * bound with its velocity zeroed; x evaluated; p replaced where
+ * e(x) < e(p); gbest = argmin e(p), lowest index on ties.  iteration = 0
+ * initialises x uniform, v = 0, p = x.  Asynchronous. */
+int sevo_pso_step(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
+                  const sevo_pso_state *st, const sevo_pso_params *par,
+                  int32_t precision, void *stream);
+
+/* ---- whole runs ---- */
+
+typedef struct {
+    sevo_problem prob;
+    uint32_t instance;
+    uint32_t run_uid;      /* Philox key word 0 of the run */
+    int32_t algo;          /* SEVO_ALGO_* */
+    int32_t np;            /* population / swarm size */
+    int64_t budget;        /* function evaluations; whole generations are run */
+    double F, CR;          /* DE */
+    double w, c1, c2, vmax;/* PSO */
+    double p;              /* SHADE: pbest fraction (top max(2, round(p NP))) */
+    int32_t H;             /* SHADE: memory size (1 .. 16) */
+} sevo_run_desc;
+
+typedef struct {
+    double best_e;         /* error of the best of the first `budget` evaluations;
+                              recomputed in double on the GPU once below 1e-6 */
+    float best_e32;        /* the same best as the single-precision path saw it */
+    int32_t success;       /* best_e <= 1e-8 */
+    int64_t fes;           /* evaluations made (the last generation may overshoot) */
+    int32_t generations;   /* generations after initialisation */
+    int32_t reserved;
+} sevo_run_result;
+
+/* Run n_runs independent runs to their budgets in persistent fused kernels
+ * (precision FP32: single-precision state, double-precision shift and final
+ * check; FP64: everything double).
+ *   results  device, [n_runs] sevo_run_result.
+ *   trace    optional device [n_runs][trace_len] float: best error after
+ *            200 (k+1) evaluations, NaN where the run made fewer.
+ *   best_x   optional device [n_runs][max_dim] double: best point.
+ * Asynchronous on `stream`. */
+int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+             sevo_run_result *results, float *trace, int64_t trace_len,
+             double *best_x, int32_t max_dim, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEVO_H */

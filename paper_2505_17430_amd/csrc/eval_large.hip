@@ -1,0 +1,312 @@
+// eval_large.hip -- evaluation of high-dimensional points (D > 120, up to
+// 1024) as a tiled GEMM Z = M * (X - o 1^T) fused with the objective.
+//
+// A workgroup (4 waves) owns a 128-row x 128-point tile of Z.  The K loop
+// stages 32 coordinates of the shifted points in LDS (shift in double, one
+// rounding to float), shared by the 4 waves; each wave streams its own 32
+// rows of M (two 16-row MFMA tiles) from L2 and accumulates 2 x 8 MFMA tiles.
+// Precision variants:
+//   FP32        v_mfma_f32_16x16x4_f32 on float operands;
+//   split bf16  every float is split into hi = bf16(f) and lo = bf16(f - hi);
+//               z += Mhi dhi + Mhi dlo + Mlo dhi on v_mfma_f32_16x16x32_bf16,
+//               accumulated in float (the lo*lo term is below float rounding).
+// After the K loop each wave folds its rows into compensated per-point
+// partial sums; the workgroup writes one partial record per (row block,
+// point), and a second pass merges the row blocks in a fixed order and adds
+// Rosenbrock's terms that straddle two row blocks.
+//
+// MFMA 16x16x32 bf16 operand layout (lane l of 64):
+//   A (16 x 32): A[l % 16][8 (l / 16) + e], e = 0..7 (eight bf16 per lane)
+//   B (32 x 16): B[8 (l / 16) + e][l % 16]
+//   D (16 x 16): as for the 16x16x4 f32 instruction.
+#include "runtime.h"
+
+namespace sevo {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int xcd_remap_l(int b, int G)
+{
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ int find_item_l(const EvalDesc *__restrict__ items, int n_items, int L)
+{
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].block0 <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int KC = 32;                 // coordinates per K chunk
+constexpr int PT = LARGE_POINTS;       // points per workgroup
+constexpr int CT = PT / 16;            // column tiles per wave
+constexpr int SB = PT + 16;            // float staging row stride (bank offset 16)
+constexpr int SK = KC + 8;             // bf16 staging row stride (80 bytes)
+
+template <int FUNC>
+__device__ __forceinline__ void fold_rows(const floatx4 (&z)[2][CT], int rt0, int w, int lane,
+                                          int dim, const float *__restrict__ tab,
+                                          const float (*sZ0)[PT], const SchwefelConst<float> &K,
+                                          float (*sAcc)[PT][5])
+{
+    const int kq = lane >> 4, pc = lane & 15;
+    const int src = (lane + 16) & 63;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        Acc<float> a;
+        a.init();
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int rbase = (rt0 + rt) * 16 + kq * 4;
+            float nb3 = 0.f;
+            if constexpr (FUNC == ROSENBROCK) {
+                const float same = __shfl(z[rt][c][0], src, 64);
+                if (rt == 0) {
+                    const float nxt = __shfl(z[1][c][0], src, 64);
+                    nb3 = kq < 3 ? same : nxt;
+                } else {
+                    nb3 = kq < 3 ? same : (w < 3 ? sZ0[w + 1][c * 16 + pc] : 0.f);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = rbase + j;
+                if (r < dim) {
+                    const float zn = j < 3 ? z[rt][c][j < 3 ? j + 1 : 0] : nb3;
+                    // the last row of the workgroup pairs with the next row block:
+                    // that term is added by the combine pass
+                    const bool boundary = (rt == 1 && kq == 3 && j == 3 && w == 3);
+                    add_term<FUNC>(a, z[rt][c][j], zn, (r + 1 < dim) && !boundary, tab[r], K);
+                }
+            }
+        }
+        merge_xor(a, 16);
+        merge_xor(a, 32);
+        if (kq == 0) {
+            float *q = sAcc[w][c * 16 + pc];
+            q[0] = a.s1;
+            q[1] = a.c1;
+            q[2] = a.s2;
+            q[3] = a.c2;
+            q[4] = __int_as_float(a.neg | (a.zero << 1));
+        }
+    }
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__ items, int n_items,
+                                                    int total_blocks, Consts K)
+{
+    __shared__ float sB[BF16 ? 1 : KC * SB];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[BF16 ? PT * SK : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sBl[BF16 ? PT * SK : 8];
+    __shared__ float sZ0[4][PT];
+    __shared__ float sZL[PT];
+    __shared__ float sAcc[4][PT][5];
+    __shared__ double sO[KC];
+
+    const int L = xcd_remap_l(blockIdx.x, total_blocks);
+    const EvalDesc &it = items[find_item_l(items, n_items, L)];
+    const int dim = it.dim, n = it.n, RB = it.rb;
+    const int64_t ld = it.ld;
+    const int local = L - it.block0;
+    const int rb = local % RB, pb = local / RB;
+    const int p_base = pb * PT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = lane >> 4, pc = lane & 15;
+    const int RT = (dim + 15) / 16, KS = (dim + 3) / 4, K32 = (dim + 31) / 32;
+    const int rt0 = rb * 8 + w * 2;
+    const bool act0 = rt0 < RT, act1 = rt0 + 1 < RT;
+    const float *__restrict__ X = static_cast<const float *>(it.x);
+
+    floatx4 z[2][CT];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) z[rt][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < dim; k0 += KC) {
+        __syncthreads();
+        if (threadIdx.x < KC) sO[threadIdx.x] = (k0 + (int)threadIdx.x < dim) ? it.o[k0 + threadIdx.x] : 0.0;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < KC * PT; idx += 256) {
+            const int kk = idx / PT, p = idx % PT;
+            const int k = k0 + kk, pg = p_base + p;
+            float v = 0.f;
+            if (k < dim && pg < n) v = (float)((double)X[(int64_t)k * ld + pg] - sO[kk]);
+            if constexpr (!BF16) {
+                sB[kk * SB + p] = v;
+            } else {
+                const uint16_t hi = to_bf16_rne(v);
+                sBh[p * SK + kk] = hi;
+                sBl[p * SK + kk] = to_bf16_rne(v - from_bf16(hi));
+            }
+        }
+        __syncthreads();
+        if (act0) {
+            if constexpr (!BF16) {
+#pragma unroll
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    const int ksg = k0 / 4 + ks;
+                    if (ksg < KS) {
+                        const float a0 = it.Mfrag[((int64_t)rt0 * KS + ksg) * 64 + lane];
+                        const float a1 = act1 ? it.Mfrag[((int64_t)(rt0 + 1) * KS + ksg) * 64 + lane] : 0.f;
+#pragma unroll
+                        for (int c = 0; c < CT; ++c) {
+                            const float b = sB[(ks * 4 + kq) * SB + c * 16 + pc];
+                            z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, z[0][c], 0, 0, 0);
+                            z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, z[1][c], 0, 0, 0);
+                        }
+                    }
+                }
+            } else {
+                const int kk = k0 / KC;
+                const uint16_t *Mh = reinterpret_cast<const uint16_t *>(it.Mbf);
+                const int64_t lo_off = (int64_t)RT * K32 * 512;
+                const int64_t i0 = (((int64_t)rt0 * K32 + kk) * 64 + lane) * 8;
+                const int64_t i1 = (((int64_t)(act1 ? rt0 + 1 : rt0) * K32 + kk) * 64 + lane) * 8;
+                const bf16x8 ah0 = *reinterpret_cast<const bf16x8 *>(Mh + i0);
+                const bf16x8 al0 = *reinterpret_cast<const bf16x8 *>(Mh + lo_off + i0);
+                bf16x8 ah1 = *reinterpret_cast<const bf16x8 *>(Mh + i1);
+                bf16x8 al1 = *reinterpret_cast<const bf16x8 *>(Mh + lo_off + i1);
+                if (!act1) { ah1 = bf16x8{}; al1 = bf16x8{}; }
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const int off = (c * 16 + pc) * SK + kq * 8;
+                    const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sBh + off);
+                    const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBl + off);
+                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, z[0][c], 0, 0, 0);
+                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, z[0][c], 0, 0, 0);
+                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, z[0][c], 0, 0, 0);
+                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z[1][c], 0, 0, 0);
+                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z[1][c], 0, 0, 0);
+                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z[1][c], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    // first row of each wave (Rosenbrock neighbours across waves), last row
+    // of the workgroup (neighbour in the next row block)
+    if (kq == 0)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) sZ0[w][c * 16 + pc] = z[0][c][0];
+    if (w == 3 && kq == 3)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) sZL[c * 16 + pc] = z[1][c][3];
+    __syncthreads();
+    switch (it.func) {
+    case ELLIPSOID: fold_rows<ELLIPSOID>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    case ROSENBROCK: fold_rows<ROSENBROCK>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    case RASTRIGIN: fold_rows<RASTRIGIN>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    case SCHWEFEL: fold_rows<SCHWEFEL>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    case GRIEWANK: fold_rows<GRIEWANK>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    default: fold_rows<ACKLEY>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    }
+    __syncthreads();
+    if (threadIdx.x < PT) {
+        const int p = threadIdx.x, pg = p_base + p;
+        if (pg < n) {
+            float s1 = sAcc[0][p][0], c1 = sAcc[0][p][1], s2 = sAcc[0][p][2], c2 = sAcc[0][p][3];
+            int fl = __float_as_int(sAcc[0][p][4]);
+            for (int q = 1; q < 4; ++q) {
+                merge(s1, c1, sAcc[q][p][0], sAcc[q][p][1]);
+                merge(s2, c2, sAcc[q][p][2], sAcc[q][p][3]);
+                const int f2 = __float_as_int(sAcc[q][p][4]);
+                fl = ((fl ^ f2) & 1) | ((fl | f2) & 2);
+            }
+            float *out = it.part + ((int64_t)rb * n + pg) * 8;
+            out[0] = s1;
+            out[1] = c1;
+            out[2] = s2;
+            out[3] = c2;
+            out[4] = __int_as_float(fl);
+            out[5] = sZ0[0][p];
+            out[6] = sZL[p];
+            out[7] = 0.f;
+        }
+    }
+}
+
+template <int FUNC>
+__device__ __forceinline__ float combine_point(const float *__restrict__ P, int n, int pg, int RB,
+                                               int dim, const SchwefelConst<float> &K)
+{
+    Acc<float> a;
+    a.init();
+    for (int rb = 0; rb < RB; ++rb) {
+        const float *q = P + ((int64_t)rb * n + pg) * 8;
+        merge(a.s1, a.c1, q[0], q[1]);
+        merge(a.s2, a.c2, q[2], q[3]);
+        const int f2 = __float_as_int(q[4]);
+        a.neg ^= f2 & 1;
+        a.zero |= f2 >> 1;
+        if constexpr (FUNC == ROSENBROCK) {
+            if (rb + 1 < RB) {
+                const float zlast = q[6];
+                const float znext = P[((int64_t)(rb + 1) * n + pg) * 8 + 5];
+                add_term<ROSENBROCK>(a, zlast, znext, true, 0.f, K);
+            }
+        }
+    }
+    return finalize<FUNC>(a, dim);
+}
+
+__global__ __launch_bounds__(256) void k_eval_large_combine(const EvalDesc *__restrict__ items,
+                                                            int n_items, int total_blocks, Consts K)
+{
+    const int L = xcd_remap_l(blockIdx.x, total_blocks);
+    const EvalDesc &it = items[find_item_l(items, n_items, L)];
+    const int pg = (L - it.block0) * 256 + threadIdx.x;
+    if (pg >= it.n) return;
+    float e;
+    switch (it.func) {
+    case ELLIPSOID: e = combine_point<ELLIPSOID>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    case ROSENBROCK: e = combine_point<ROSENBROCK>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    case RASTRIGIN: e = combine_point<RASTRIGIN>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    case SCHWEFEL: e = combine_point<SCHWEFEL>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    case GRIEWANK: e = combine_point<GRIEWANK>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    default: e = combine_point<ACKLEY>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    }
+    static_cast<float *>(it.err)[pg] = e;
+}
+
+hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blocks,
+                             bool split_bf16, const Consts &k, hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    if (split_bf16)
+        hipLaunchKernelGGL(k_eval_large<true>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
+                           total_blocks, k);
+    else
+        hipLaunchKernelGGL(k_eval_large<false>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
+                           total_blocks, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_large_combine(const EvalDesc *d_items, int n_items, int total_blocks,
+                                     const Consts &k, hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_large_combine, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
+                       total_blocks, k);
+    return hipGetLastError();
+}
+
+}  // namespace sevo

@@ -1,0 +1,66 @@
+// runtime.h -- internal interface between the host runtime (runtime.hip) and
+// the kernel launchers (eval.hip, steps.hip, run.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+#include "objective.h"
+
+namespace sevo {
+
+// Largest dimension of the small-D evaluation path: its rotation (padded to
+// 16-row tiles by 4-column steps) lives in LDS, <= 62 KB.
+constexpr int SMALL_D_MAX = 120;
+constexpr int MAX_DIM = 1024;
+
+// One evaluation item as the kernels see it (a population of one
+// (function, dimension, instance)).
+struct EvalDesc {
+    const void *x;          // [dim][ld], float or double
+    void *err;              // [n], float or double
+    const double *o;        // [dim]
+    const float *Mfrag;     // [RT][KS][64] MFMA A-operand fragments of M (float)
+    const float *tab;       // [RT * 16] per-row table (ellipsoid weight, 1/sqrt(i))
+    const double *M64;      // [dim][dim] row-major
+    const uint16_t *Mbf;    // bf16 hi block then lo block, each [RT][KS32][64][8]
+    float *part;            // large-D partial sums [RB][n][8] (workspace)
+    int64_t ld;
+    int32_t n;
+    int32_t func;
+    int32_t dim;
+    int32_t block0;         // first logical block of this item
+    int32_t nblocks;        // logical blocks of this item
+    int32_t rb;             // large-D: row blocks
+};
+
+struct Consts {
+    SchwefelConst<float> kf;
+    SchwefelConst<double> kd;
+};
+
+Consts make_consts();
+
+inline int ks_of(int dim) { return (dim + 3) / 4; }
+inline int rt_of(int dim) { return (dim + 15) / 16; }
+inline int ks32_of(int dim) { return (dim + 31) / 32; }
+
+// eval.hip
+constexpr int SMALL_TILE_POINTS = 128;   // points per workgroup iteration (4 waves x 32)
+int small_blocks_for(int n, int tiles_per_block);
+hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_blocks,
+                             int tiles_per_block, const Consts &k, hipStream_t s);
+
+constexpr int LARGE_ROWS = 128;          // rows of z per workgroup (4 waves x 32)
+constexpr int LARGE_POINTS = 128;        // points per workgroup
+hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blocks,
+                             bool split_bf16, const Consts &k, hipStream_t s);
+hipError_t launch_eval_large_combine(const EvalDesc *d_items, int n_items, int total_blocks,
+                                     const Consts &k, hipStream_t s);
+
+constexpr int F64_POINTS = 64;           // points per workgroup of the double path
+hipError_t launch_eval_f64(const EvalDesc *d_items, int n_items, int total_blocks,
+                           const Consts &k, hipStream_t s);
+
+}  // namespace sevo

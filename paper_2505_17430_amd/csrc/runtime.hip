@@ -1,0 +1,677 @@
+// runtime.hip -- host runtime behind the C ABI of include/sevo.h: contexts,
+// error plumbing, the instance generator and cache, descriptor staging and
+// the dispatch of evaluation batches to the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sevo.h"
+#include "runtime.h"
+#include "state.h"
+
+using namespace sevo;
+
+// ---------------------------------------------------------------------------
+// Instances
+
+namespace sevo {
+
+// Orthogonal factor of a Householder QR of the n x n row-major matrix G with
+// every diagonal entry of R made positive (so the factor is unique).  The
+// reflectors are stored column by column and accumulated backwards onto the
+// identity.
+static void orthogonal_factor(int n, std::vector<double> G, std::vector<double> &Q)
+{
+    std::vector<std::vector<double>> refl;   // refl[k][r - k], unit norm
+    std::vector<int> flip(n, 0);
+    refl.reserve(n);
+    auto at = [&](int r, int c) -> double & { return G[(size_t)r * n + c]; };
+    for (int k = 0; k < n; ++k) {
+        std::vector<double> v(n - k);
+        double nrm = 0.0;
+        for (int r = k; r < n; ++r) { v[r - k] = at(r, k); nrm += v[r - k] * v[r - k]; }
+        nrm = std::sqrt(nrm);
+        if (k == n - 1 || nrm == 0.0) {
+            // last column (or a zero one): no reflector; R_kk = at(k, k)
+            refl.emplace_back();
+            flip[k] = at(k, k) < 0.0;
+            continue;
+        }
+        const double alpha = v[0] >= 0.0 ? -nrm : nrm;   // R_kk after the reflection
+        v[0] -= alpha;
+        double vn = 0.0;
+        for (double e : v) vn += e * e;
+        vn = std::sqrt(vn);
+        if (vn == 0.0) { refl.emplace_back(); flip[k] = at(k, k) < 0.0; continue; }
+        for (double &e : v) e /= vn;
+        for (int c = k; c < n; ++c) {
+            double dot = 0.0;
+            for (int r = k; r < n; ++r) dot += v[r - k] * at(r, c);
+            for (int r = k; r < n; ++r) at(r, c) -= 2.0 * dot * v[r - k];
+        }
+        flip[k] = alpha < 0.0;
+        refl.push_back(std::move(v));
+    }
+    // Q = H_0 H_1 ... H_{n-1} I, applied right to left.
+    Q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    for (int k = n - 1; k >= 0; --k) {
+        const std::vector<double> &v = refl[k];
+        if (v.empty()) continue;
+        for (int c = 0; c < n; ++c) {
+            double dot = 0.0;
+            for (int r = k; r < n; ++r) dot += v[r - k] * Q[(size_t)r * n + c];
+            for (int r = k; r < n; ++r) Q[(size_t)r * n + c] -= 2.0 * dot * v[r - k];
+        }
+    }
+    for (int j = 0; j < n; ++j)
+        if (flip[j])
+            for (int r = 0; r < n; ++r) Q[(size_t)r * n + j] = -Q[(size_t)r * n + j];
+}
+
+static void generate_instance(int func, int dim, uint32_t inst, uint64_t inst_seed,
+                              std::vector<double> &o, std::vector<double> &M)
+{
+    const uint32_t k1 = fold_seed(inst_seed);
+    o.assign(dim, 0.0);
+    for (int j = 0; j < dim; j += 2) {
+        const u32x4 w = draw(inst, k1, (uint32_t)func, (uint32_t)dim, TAG_SHIFT_O, (uint32_t)(j >> 1));
+        o[j] = -80.0 + 160.0 * u53(w.x, w.y);
+        if (j + 1 < dim) o[j + 1] = -80.0 + 160.0 * u53(w.z, w.w);
+    }
+    const size_t nn = (size_t)dim * dim;
+    std::vector<double> G(nn);
+    const double two_pi = 6.283185307179586476925287;
+    for (size_t e = 0; e < nn; e += 2) {
+        const u32x4 w = draw(inst, k1, (uint32_t)func, (uint32_t)dim, TAG_ROT_N, (uint32_t)(e >> 1));
+        const double rad = std::sqrt(-2.0 * std::log(1.0 - u53(w.x, w.y)));
+        const double ang = two_pi * u53(w.z, w.w);
+        G[e] = rad * std::cos(ang);
+        if (e + 1 < nn) G[e + 1] = rad * std::sin(ang);
+    }
+    orthogonal_factor(dim, std::move(G), M);
+}
+
+Consts make_consts()
+{
+    Consts k;
+    const double s = SCHWEFEL_S, a = std::sqrt(s);
+    const double c = s * std::sin(a);
+    const double s500 = std::sin(std::sqrt(500.0));
+    SchwefelConst<double> d;
+    d.s = s; d.a = a; d.sa = std::sin(a); d.ca = std::cos(a); d.c = c;
+    d.zhi = 500.0 - s; d.zlo = -500.0 - s;
+    d.gp = c - 500.0 * s500; d.gm = c + 500.0 * s500;
+    d.lambda = SCHWEFEL_LAMBDA; d.nega_s = -s;
+    k.kd = d;
+    k.kf = SchwefelConst<float>{(float)d.s, (float)d.a, (float)d.sa, (float)d.ca, (float)d.c,
+                                (float)d.zhi, (float)d.zlo, (float)d.gp, (float)d.gm,
+                                (float)d.lambda, (float)d.nega_s};
+    return k;
+}
+
+}  // namespace sevo
+
+// ---------------------------------------------------------------------------
+// Context
+
+struct DevInstance {
+    int func = 0, dim = 0;
+    std::vector<double> o, M;
+    double *d_o = nullptr, *d_M64 = nullptr;
+    float *d_Mfrag = nullptr, *d_tab = nullptr;
+    uint16_t *d_Mbf = nullptr;
+};
+
+struct DescSlot {
+    EvalDesc *h = nullptr, *d = nullptr;
+    size_t cap = 0, used = 0;
+    hipEvent_t done = nullptr;
+};
+
+struct sevo_ctx {
+    int device = 0;
+    uint64_t base_seed = 0, inst_seed = 0;
+    std::string err;
+    std::map<std::tuple<int, int, uint32_t>, std::unique_ptr<DevInstance>> cache;
+    std::vector<DescSlot> slots;
+    int next_slot = 0;
+    int last_slot = -1;
+    Consts consts;
+    int tiles_per_block = 0;     // 0 = automatic
+    sevo::Workspace ws;
+};
+
+static std::string g_create_error;
+
+static int fail(sevo_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail((ctx), SEVO_EDEVICE, "%s: %s", #call, hipGetErrorString(_e));       \
+    } while (0)
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int check_problem(sevo_ctx *ctx, const sevo_problem *p)
+{
+    if (!p) return fail(ctx, SEVO_EINVAL, "problem is NULL");
+    if (p->func < 0 || p->func >= NFUNC) return fail(ctx, SEVO_EINVAL, "unknown function %d", p->func);
+    if (p->dim < 2 || p->dim > MAX_DIM)
+        return fail(ctx, SEVO_EINVAL, "dimension %d outside [2, %d]", p->dim, MAX_DIM);
+    if (!(p->lb < p->ub) || !std::isfinite(p->lb) || !std::isfinite(p->ub))
+        return fail(ctx, SEVO_EINVAL, "bounds [%g, %g] invalid", p->lb, p->ub);
+    return SEVO_OK;
+}
+
+int upload_instance(sevo_ctx *ctx, DevInstance &I)
+{
+    const int D = I.dim;
+    const int RT = rt_of(D), KS = ks_of(D), K32 = ks32_of(D);
+    std::vector<float> frag((size_t)RT * KS * 64, 0.f);
+    for (int rt = 0; rt < RT; ++rt)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const int r = rt * 16 + (l & 15), c = ks * 4 + (l >> 4);
+                if (r < D && c < D) frag[((size_t)rt * KS + ks) * 64 + l] = (float)I.M[(size_t)r * D + c];
+            }
+    std::vector<float> tab((size_t)RT * 16, 0.f);
+    for (int r = 0; r < D; ++r) {
+        if (I.func == ELLIPSOID) tab[r] = (float)std::pow(10.0, 6.0 * r / (double)(D - 1));
+        else if (I.func == GRIEWANK) tab[r] = (float)(1.0 / std::sqrt((double)(r + 1)));
+    }
+    // bf16 hi/lo split of each float of M in the A-operand order of the
+    // 16x16x32 bf16 MFMA (lane l holds row l % 16, columns 8 (l / 16) + 0..7):
+    // hi block [RT][K32][64][8] followed by the lo block.
+    const size_t half = (size_t)RT * K32 * 64 * 8;
+    std::vector<uint16_t> bf(2 * half, 0);
+    auto to_bf16 = [](float f) -> uint16_t {     // round to nearest even
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    };
+    auto from_bf16 = [](uint16_t h) -> float {
+        uint32_t u = (uint32_t)h << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    };
+    for (int rt = 0; rt < RT; ++rt)
+        for (int kk = 0; kk < K32; ++kk)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e) {
+                    const int r = rt * 16 + (l & 15), c = kk * 32 + (l >> 4) * 8 + e;
+                    float f = 0.f;
+                    if (r < D && c < D) f = (float)I.M[(size_t)r * D + c];
+                    const uint16_t hi = to_bf16(f);
+                    const size_t at = (((size_t)rt * K32 + kk) * 64 + l) * 8 + e;
+                    bf[at] = hi;
+                    bf[half + at] = to_bf16(f - from_bf16(hi));
+                }
+    HIP_TRY(ctx, hipMalloc(&I.d_o, sizeof(double) * D));
+    HIP_TRY(ctx, hipMalloc(&I.d_M64, sizeof(double) * (size_t)D * D));
+    HIP_TRY(ctx, hipMalloc(&I.d_Mfrag, sizeof(float) * frag.size()));
+    HIP_TRY(ctx, hipMalloc(&I.d_tab, sizeof(float) * tab.size()));
+    HIP_TRY(ctx, hipMalloc(&I.d_Mbf, sizeof(uint16_t) * bf.size()));
+    HIP_TRY(ctx, hipMemcpy(I.d_o, I.o.data(), sizeof(double) * D, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(I.d_M64, I.M.data(), sizeof(double) * (size_t)D * D, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(I.d_Mfrag, frag.data(), sizeof(float) * frag.size(), hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(I.d_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(I.d_Mbf, bf.data(), sizeof(uint16_t) * bf.size(), hipMemcpyHostToDevice));
+    return SEVO_OK;
+}
+
+void free_instance(DevInstance &I)
+{
+    (void)hipFree(I.d_o);
+    (void)hipFree(I.d_M64);
+    (void)hipFree(I.d_Mfrag);
+    (void)hipFree(I.d_tab);
+    (void)hipFree(I.d_Mbf);
+    I.d_o = I.d_M64 = nullptr;
+    I.d_Mfrag = I.d_tab = nullptr;
+    I.d_Mbf = nullptr;
+}
+
+int get_instance(sevo_ctx *ctx, const sevo_problem *p, uint32_t inst, DevInstance **out)
+{
+    auto key = std::make_tuple((int)p->func, (int)p->dim, inst);
+    auto itr = ctx->cache.find(key);
+    if (itr != ctx->cache.end()) { *out = itr->second.get(); return SEVO_OK; }
+    auto I = std::make_unique<DevInstance>();
+    I->func = p->func;
+    I->dim = p->dim;
+    generate_instance(p->func, p->dim, inst, ctx->inst_seed, I->o, I->M);
+    int rc = upload_instance(ctx, *I);
+    if (rc != SEVO_OK) { free_instance(*I); return rc; }
+    *out = I.get();
+    ctx->cache.emplace(key, std::move(I));
+    return SEVO_OK;
+}
+
+// Stage a descriptor table in device memory.  Slots rotate; a slot is
+// rewritten only after the kernels that read it have finished.  A table equal
+// to the previous call's is reused in place (read-only), with no copy.
+int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t stream,
+                const EvalDesc **d_out, int *slot_out)
+{
+    const size_t n = descs.size();
+    if (ctx->last_slot >= 0) {
+        DescSlot &s = ctx->slots[ctx->last_slot];
+        if (s.used == n && std::memcmp(s.h, descs.data(), n * sizeof(EvalDesc)) == 0) {
+            *d_out = s.d;
+            *slot_out = ctx->last_slot;
+            return SEVO_OK;
+        }
+    }
+    const int idx = ctx->next_slot;
+    ctx->next_slot = (ctx->next_slot + 1) % (int)ctx->slots.size();
+    DescSlot &s = ctx->slots[idx];
+    HIP_TRY(ctx, hipEventSynchronize(s.done));
+    if (s.cap < n) {
+        (void)hipHostFree(s.h);
+        (void)hipFree(s.d);
+        s.h = nullptr; s.d = nullptr; s.cap = 0;
+        const size_t cap = std::max<size_t>(n, 64);
+        HIP_TRY(ctx, hipHostMalloc(&s.h, cap * sizeof(EvalDesc), hipHostMallocDefault));
+        HIP_TRY(ctx, hipMalloc(&s.d, cap * sizeof(EvalDesc)));
+        s.cap = cap;
+    }
+    std::memcpy(s.h, descs.data(), n * sizeof(EvalDesc));
+    s.used = n;
+    HIP_TRY(ctx, hipMemcpyAsync(s.d, s.h, n * sizeof(EvalDesc), hipMemcpyHostToDevice, stream));
+    ctx->last_slot = idx;
+    *d_out = s.d;
+    *slot_out = idx;
+    return SEVO_OK;
+}
+
+int finish_slot(sevo_ctx *ctx, int slot, hipStream_t stream)
+{
+    HIP_TRY(ctx, hipEventRecord(ctx->slots[slot].done, stream));
+    return SEVO_OK;
+}
+
+int auto_tpb(sevo_ctx *ctx, long total_tiles)
+{
+    if (ctx->tiles_per_block > 0) return ctx->tiles_per_block;
+    long t = total_tiles / 2048;
+    return (int)std::min<long>(8, std::max<long>(1, t));
+}
+
+}  // namespace
+
+// Evaluate a list of (item, instance) pairs already validated.
+namespace sevo {
+int eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items, int precision,
+               hipStream_t stream);
+}
+
+int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items,
+                     int precision, hipStream_t stream)
+{
+    // group: FP64 -> one launch; FP32/BF16 small D -> one launch per KS;
+    // large D -> one launch pair.
+    std::map<int, std::vector<EvalDesc>> small;
+    std::vector<EvalDesc> f64, large;
+    for (const auto &pr : items) {
+        const EvalDesc &d = pr.first;
+        if (d.n <= 0) continue;
+        if (precision == SEVO_FP64) f64.push_back(d);
+        else if (d.dim <= SMALL_D_MAX) small[ks_of(d.dim)].push_back(d);
+        else large.push_back(d);
+    }
+    for (auto &kv : small) {
+        std::vector<EvalDesc> &v = kv.second;
+        long tiles = 0;
+        for (auto &d : v) tiles += (d.n + SMALL_TILE_POINTS - 1) / SMALL_TILE_POINTS;
+        const int tpb = auto_tpb(ctx, tiles);
+        int blocks = 0;
+        for (auto &d : v) {
+            d.block0 = blocks;
+            d.nblocks = small_blocks_for(d.n, tpb);
+            blocks += d.nblocks;
+        }
+        const EvalDesc *dd;
+        int slot;
+        int rc = stage_descs(ctx, v, stream, &dd, &slot);
+        if (rc) return rc;
+        HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), kv.first, blocks, tpb, ctx->consts, stream));
+        if ((rc = finish_slot(ctx, slot, stream))) return rc;
+    }
+    if (!f64.empty()) {
+        int blocks = 0;
+        for (auto &d : f64) {
+            d.block0 = blocks;
+            d.nblocks = (d.n + F64_POINTS - 1) / F64_POINTS;
+            blocks += d.nblocks;
+        }
+        const EvalDesc *dd;
+        int slot;
+        int rc = stage_descs(ctx, f64, stream, &dd, &slot);
+        if (rc) return rc;
+        HIP_TRY(ctx, launch_eval_f64(dd, (int)f64.size(), blocks, ctx->consts, stream));
+        if ((rc = finish_slot(ctx, slot, stream))) return rc;
+    }
+    if (!large.empty()) {
+        int rc = eval_large(ctx, large, precision == SEVO_SPLIT_BF16, stream);
+        if (rc) return rc;
+    }
+    return SEVO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Large-D evaluation: partial sums per 64-row block of z, then a combine pass.
+int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStream_t stream)
+{
+    size_t part_elems = 0;
+    int blocks = 0;
+    for (auto &d : v) {
+        d.rb = (d.dim + LARGE_ROWS - 1) / LARGE_ROWS;
+        d.block0 = blocks;
+        d.nblocks = d.rb * ((d.n + LARGE_POINTS - 1) / LARGE_POINTS);
+        blocks += d.nblocks;
+        part_elems += (size_t)d.rb * d.n * 8;
+    }
+    float *part = nullptr;
+    int rc = ctx->ws.get(ctx, WS_PARTIAL, part_elems * sizeof(float), (void **)&part);
+    if (rc) return rc;
+    size_t off = 0;
+    int cblocks = 0;
+    for (auto &d : v) {
+        d.part = part + off;
+        off += (size_t)d.rb * d.n * 8;
+    }
+    const EvalDesc *dd;
+    int slot;
+    if ((rc = stage_descs(ctx, v, stream, &dd, &slot))) return rc;
+    HIP_TRY(ctx, launch_eval_large(dd, (int)v.size(), blocks, bf16, ctx->consts, stream));
+    if ((rc = finish_slot(ctx, slot, stream))) return rc;
+    // combine: one thread per point, blocks of 256 points
+    std::vector<EvalDesc> c = v;
+    for (auto &d : c) {
+        d.block0 = cblocks;
+        d.nblocks = (d.n + 255) / 256;
+        cblocks += d.nblocks;
+    }
+    if ((rc = stage_descs(ctx, c, stream, &dd, &slot))) return rc;
+    HIP_TRY(ctx, launch_eval_large_combine(dd, (int)c.size(), cblocks, ctx->consts, stream));
+    if ((rc = finish_slot(ctx, slot, stream))) return rc;
+    return SEVO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace
+
+int sevo::Workspace::get(sevo_ctx *ctx, int which, size_t bytes, void **out)
+{
+    Buf &b = bufs[which];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            HIP_TRY(ctx, hipDeviceSynchronize());
+            (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        const size_t cap = std::max<size_t>(bytes, 1 << 20);
+        HIP_TRY(ctx, hipMalloc(&b.ptr, cap));
+        b.bytes = cap;
+    }
+    *out = b.ptr;
+    return SEVO_OK;
+}
+
+void sevo::Workspace::release()
+{
+    for (auto &b : bufs) {
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+}
+
+int sevo::set_error(sevo_ctx *ctx, int code, const char *msg)
+{
+    return fail(ctx, code, "%s", msg);
+}
+
+int sevo::lookup_instance(sevo_ctx *ctx, const sevo_problem *p, uint32_t inst, InstanceView *out)
+{
+    DevInstance *I = nullptr;
+    int rc = get_instance(ctx, p, inst, &I);
+    if (rc) return rc;
+    out->o = I->d_o;
+    out->M64 = I->d_M64;
+    out->Mfrag = I->d_Mfrag;
+    out->tab = I->d_tab;
+    out->Mbf = I->d_Mbf;
+    return SEVO_OK;
+}
+
+const Consts &sevo::ctx_consts(sevo_ctx *ctx) { return ctx->consts; }
+uint32_t sevo::ctx_seed32(sevo_ctx *ctx) { return fold_seed(ctx->base_seed); }
+Workspace &sevo::ctx_ws(sevo_ctx *ctx) { return ctx->ws; }
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int sevo_create(sevo_ctx **out, int32_t hip_device, uint64_t base_seed, uint64_t instance_seed)
+{
+    if (!out) return fail(nullptr, SEVO_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(nullptr, SEVO_EDEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= n)
+        return fail(nullptr, SEVO_EINVAL, "device %d not in [0, %d)", hip_device, n);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, hip_device);
+    if (e != hipSuccess)
+        return fail(nullptr, SEVO_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, SEVO_EUNSUPPORTED, "device %d is %s; this library is built for gfx950",
+                    hip_device, prop.gcnArchName);
+    auto ctx = std::make_unique<sevo_ctx>();
+    ctx->device = hip_device;
+    ctx->base_seed = base_seed;
+    ctx->inst_seed = instance_seed;
+    ctx->consts = make_consts();
+    DeviceGuard g(hip_device);
+    ctx->slots.resize(16);
+    for (auto &s : ctx->slots) {
+        e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return fail(nullptr, SEVO_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    *out = ctx.release();
+    return SEVO_OK;
+}
+
+int sevo_destroy(sevo_ctx *ctx)
+{
+    if (!ctx) return SEVO_OK;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto &kv : ctx->cache) free_instance(*kv.second);
+        for (auto &s : ctx->slots) {
+            (void)hipHostFree(s.h);
+            (void)hipFree(s.d);
+            if (s.done) (void)hipEventDestroy(s.done);
+        }
+        ctx->ws.release();
+        sevo::release_state(ctx);
+    }
+    delete ctx;
+    return SEVO_OK;
+}
+
+const char *sevo_last_error(const sevo_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int sevo_sync(sevo_ctx *ctx, void *stream)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(ctx, hipGetLastError());
+    return SEVO_OK;
+}
+
+int sevo_instance(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance, double *o_host,
+                  double *M_host)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    int rc = check_problem(ctx, prob);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    DevInstance *I = nullptr;
+    if ((rc = get_instance(ctx, prob, instance, &I))) return rc;
+    if (o_host) std::memcpy(o_host, I->o.data(), sizeof(double) * I->dim);
+    if (M_host) std::memcpy(M_host, I->M.data(), sizeof(double) * (size_t)I->dim * I->dim);
+    return SEVO_OK;
+}
+
+int sevo_generate_instance(int32_t func, int32_t dim, uint32_t instance, uint64_t instance_seed,
+                           double *o_host, double *M_host)
+{
+    sevo_problem p{func, dim, -1.0, 1.0, 0.0};
+    int rc = check_problem(nullptr, &p);
+    if (rc) return rc;
+    if (!o_host || !M_host) return fail(nullptr, SEVO_EINVAL, "o and M must be given");
+    std::vector<double> o, M;
+    generate_instance(func, dim, instance, instance_seed, o, M);
+    std::memcpy(o_host, o.data(), sizeof(double) * dim);
+    std::memcpy(M_host, M.data(), sizeof(double) * (size_t)dim * dim);
+    return SEVO_OK;
+}
+
+int sevo_set_instance(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
+                      const double *o_host, const double *M_host)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    int rc = check_problem(ctx, prob);
+    if (rc) return rc;
+    if (!o_host || !M_host) return fail(ctx, SEVO_EINVAL, "o and M must be given");
+    for (int j = 0; j < prob->dim; ++j)
+        if (!std::isfinite(o_host[j])) return fail(ctx, SEVO_EINVAL, "o[%d] is not finite", j);
+    for (size_t j = 0; j < (size_t)prob->dim * prob->dim; ++j)
+        if (!std::isfinite(M_host[j])) return fail(ctx, SEVO_EINVAL, "M[%zu] is not finite", j);
+    DeviceGuard g(ctx->device);
+    HIP_TRY(ctx, hipDeviceSynchronize());   // the old copy may still be read
+    auto key = std::make_tuple((int)prob->func, (int)prob->dim, instance);
+    auto itr = ctx->cache.find(key);
+    if (itr != ctx->cache.end()) {
+        free_instance(*itr->second);
+        ctx->cache.erase(itr);
+    }
+    ctx->last_slot = -1;   // cached descriptor tables may point at the old copy
+    auto I = std::make_unique<DevInstance>();
+    I->func = prob->func;
+    I->dim = prob->dim;
+    I->o.assign(o_host, o_host + prob->dim);
+    I->M.assign(M_host, M_host + (size_t)prob->dim * prob->dim);
+    if ((rc = upload_instance(ctx, *I))) { free_instance(*I); return rc; }
+    ctx->cache.emplace(key, std::move(I));
+    return SEVO_OK;
+}
+
+static int check_precision(sevo_ctx *ctx, int precision)
+{
+    if (precision != SEVO_FP64 && precision != SEVO_FP32 && precision != SEVO_SPLIT_BF16)
+        return fail(ctx, SEVO_EINVAL, "unknown precision %d", precision);
+    return SEVO_OK;
+}
+
+int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
+                        int32_t precision, void *stream)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    int rc = check_precision(ctx, precision);
+    if (rc) return rc;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, SEVO_EINVAL, "bad item list");
+    DeviceGuard g(ctx->device);
+    std::vector<std::pair<EvalDesc, int>> v;
+    v.reserve(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        const sevo_eval_item &it = items[i];
+        if ((rc = check_problem(ctx, &it.prob))) return rc;
+        if (it.n < 0) return fail(ctx, SEVO_EINVAL, "item %d: n = %d", i, it.n);
+        if (it.n == 0) continue;
+        if (it.ld < it.n) return fail(ctx, SEVO_EINVAL, "item %d: ld %lld < n %d", i, (long long)it.ld, it.n);
+        if (!it.x || !it.err_out) return fail(ctx, SEVO_EINVAL, "item %d: null buffer", i);
+        DevInstance *I = nullptr;
+        if ((rc = get_instance(ctx, &it.prob, it.instance, &I))) return rc;
+        EvalDesc d{};
+        d.x = it.x;
+        d.err = it.err_out;
+        d.o = I->d_o;
+        d.Mfrag = I->d_Mfrag;
+        d.tab = I->d_tab;
+        d.M64 = I->d_M64;
+        d.Mbf = I->d_Mbf;
+        d.ld = it.ld;
+        d.n = it.n;
+        d.func = it.prob.func;
+        d.dim = it.prob.dim;
+        v.emplace_back(d, i);
+    }
+    return eval_items(ctx, v, precision, (hipStream_t)stream);
+}
+
+int sevo_evaluate(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance, const void *x,
+                  int64_t ld, int32_t n, void *err_out, int32_t precision, void *stream)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    if (!prob) return fail(ctx, SEVO_EINVAL, "problem is NULL");
+    sevo_eval_item it;
+    it.prob = *prob;
+    it.instance = instance;
+    it.n = n;
+    it.ld = ld;
+    it.x = x;
+    it.err_out = err_out;
+    return sevo_evaluate_batch(ctx, &it, 1, precision, stream);
+}
+
+}  // extern "C"
