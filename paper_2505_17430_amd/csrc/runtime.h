@@ -10,6 +10,21 @@
 
 namespace sevo {
 
+// Pointers read out of descriptors are generic; casting them to the global
+// address space lets the compiler emit global (not flat) loads and stores,
+// which do not tie up the LDS counter.
+#define SEVO_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const SEVO_GLOBAL T *gin(const void *p)
+{
+    return (const SEVO_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ SEVO_GLOBAL T *gout(void *p)
+{
+    return (SEVO_GLOBAL T *)p;
+}
+
 // Largest dimension of the small-D evaluation path: its rotation (padded to
 // 16-row tiles by 4-column steps) lives in LDS, <= 62 KB.
 constexpr int SMALL_D_MAX = 120;
@@ -47,8 +62,8 @@ inline int rt_of(int dim) { return (dim + 15) / 16; }
 inline int ks32_of(int dim) { return (dim + 31) / 32; }
 
 // eval.hip
-constexpr int SMALL_TILE_POINTS = 128;   // points per workgroup iteration (4 waves x 32)
-int small_blocks_for(int n, int tiles_per_block);
+int small_tile_points(int ks);            // points per workgroup iteration
+int small_blocks_for(int n, int ks, int tiles_per_block);
 hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_blocks,
                              int tiles_per_block, const Consts &k, hipStream_t s);
 

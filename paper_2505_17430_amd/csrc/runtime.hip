@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -133,8 +134,9 @@ struct DevInstance {
 };
 
 struct DescSlot {
-    EvalDesc *h = nullptr, *d = nullptr;
+    char *h = nullptr, *d = nullptr;
     size_t cap = 0, used = 0;
+    bool valid = false;          // device copy equals h[0, used)
     hipEvent_t done = nullptr;
 };
 
@@ -213,7 +215,7 @@ int upload_instance(sevo_ctx *ctx, DevInstance &I)
     std::vector<float> tab((size_t)RT * 16, 0.f);
     for (int r = 0; r < D; ++r) {
         if (I.func == ELLIPSOID) tab[r] = (float)std::pow(10.0, 6.0 * r / (double)(D - 1));
-        else if (I.func == GRIEWANK) tab[r] = (float)(1.0 / std::sqrt((double)(r + 1)));
+        else if (I.func == GRIEWANK) tab[r] = (float)(1.0 / (2.0 * M_PI * std::sqrt((double)(r + 1))));
     }
     // bf16 hi/lo split of each float of M in the A-operand order of the
     // 16x16x32 bf16 MFMA (lane l holds row l % 16, columns 8 (l / 16) + 0..7):
@@ -285,18 +287,29 @@ int get_instance(sevo_ctx *ctx, const sevo_problem *p, uint32_t inst, DevInstanc
     return SEVO_OK;
 }
 
-// Stage a descriptor table in device memory.  Slots rotate; a slot is
-// rewritten only after the kernels that read it have finished.  A table equal
-// to the previous call's is reused in place (read-only), with no copy.
+// Stage a descriptor table (item descriptors followed by the logical block
+// -> item map) in device memory.  Slots rotate; a slot is rewritten only
+// after the kernels that read it have finished.  A table equal to the
+// previous call's is reused in place (read-only), with no copy.
 int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t stream,
                 const EvalDesc **d_out, int *slot_out)
 {
-    const size_t n = descs.size();
-    if (ctx->last_slot >= 0) {
-        DescSlot &s = ctx->slots[ctx->last_slot];
-        if (s.used == n && std::memcmp(s.h, descs.data(), n * sizeof(EvalDesc)) == 0) {
-            *d_out = s.d;
-            *slot_out = ctx->last_slot;
+    std::vector<char> blob(descs.size() * sizeof(EvalDesc));
+    std::memcpy(blob.data(), descs.data(), blob.size());
+    int total = 0;
+    for (const auto &d : descs) total = std::max(total, d.block0 + d.nblocks);
+    std::vector<int32_t> map(total, 0);
+    for (size_t i = 0; i < descs.size(); ++i)
+        for (int b = 0; b < descs[i].nblocks; ++b) map[descs[i].block0 + b] = (int32_t)i;
+    const size_t off = blob.size();
+    blob.resize(off + map.size() * sizeof(int32_t));
+    if (!map.empty()) std::memcpy(blob.data() + off, map.data(), map.size() * sizeof(int32_t));
+    const size_t n = blob.size();
+    for (int k = 0; k < (int)ctx->slots.size() && ctx->last_slot >= 0; ++k) {
+        DescSlot &s = ctx->slots[k];
+        if (s.used == n && s.valid && std::memcmp(s.h, blob.data(), n) == 0) {
+            *d_out = reinterpret_cast<const EvalDesc *>(s.d);
+            *slot_out = k;
             return SEVO_OK;
         }
     }
@@ -308,16 +321,18 @@ int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t s
         (void)hipHostFree(s.h);
         (void)hipFree(s.d);
         s.h = nullptr; s.d = nullptr; s.cap = 0;
-        const size_t cap = std::max<size_t>(n, 64);
-        HIP_TRY(ctx, hipHostMalloc(&s.h, cap * sizeof(EvalDesc), hipHostMallocDefault));
-        HIP_TRY(ctx, hipMalloc(&s.d, cap * sizeof(EvalDesc)));
+        const size_t cap = std::max<size_t>(n, 64 * 1024);
+        HIP_TRY(ctx, hipHostMalloc((void **)&s.h, cap, hipHostMallocDefault));
+        HIP_TRY(ctx, hipMalloc((void **)&s.d, cap));
         s.cap = cap;
     }
-    std::memcpy(s.h, descs.data(), n * sizeof(EvalDesc));
+    s.valid = false;
+    std::memcpy(s.h, blob.data(), n);
     s.used = n;
-    HIP_TRY(ctx, hipMemcpyAsync(s.d, s.h, n * sizeof(EvalDesc), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(s.d, s.h, n, hipMemcpyHostToDevice, stream));
+    s.valid = true;
     ctx->last_slot = idx;
-    *d_out = s.d;
+    *d_out = reinterpret_cast<const EvalDesc *>(s.d);
     *slot_out = idx;
     return SEVO_OK;
 }
@@ -359,20 +374,21 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
     }
     for (auto &kv : small) {
         std::vector<EvalDesc> &v = kv.second;
+        const int ks = kv.first, tp = small_tile_points(ks);
         long tiles = 0;
-        for (auto &d : v) tiles += (d.n + SMALL_TILE_POINTS - 1) / SMALL_TILE_POINTS;
+        for (auto &d : v) tiles += (d.n + tp - 1) / tp;
         const int tpb = auto_tpb(ctx, tiles);
         int blocks = 0;
         for (auto &d : v) {
             d.block0 = blocks;
-            d.nblocks = small_blocks_for(d.n, tpb);
+            d.nblocks = small_blocks_for(d.n, ks, tpb);
             blocks += d.nblocks;
         }
         const EvalDesc *dd;
         int slot;
         int rc = stage_descs(ctx, v, stream, &dd, &slot);
         if (rc) return rc;
-        HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), kv.first, blocks, tpb, ctx->consts, stream));
+        HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), ks, blocks, tpb, ctx->consts, stream));
         if ((rc = finish_slot(ctx, slot, stream))) return rc;
     }
     if (!f64.empty()) {
@@ -514,6 +530,7 @@ int sevo_create(sevo_ctx **out, int32_t hip_device, uint64_t base_seed, uint64_t
     ctx->base_seed = base_seed;
     ctx->inst_seed = instance_seed;
     ctx->consts = make_consts();
+    if (const char *e = std::getenv("SEVO_TILES_PER_BLOCK")) ctx->tiles_per_block = std::atoi(e);
     DeviceGuard g(hip_device);
     ctx->slots.resize(16);
     for (auto &s : ctx->slots) {
@@ -606,6 +623,7 @@ int sevo_set_instance(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance
         ctx->cache.erase(itr);
     }
     ctx->last_slot = -1;   // cached descriptor tables may point at the old copy
+    for (auto &sl : ctx->slots) sl.valid = false;
     auto I = std::make_unique<DevInstance>();
     I->func = prob->func;
     I->dim = prob->dim;

@@ -209,15 +209,22 @@ class Context:
         self._check(self._L.sevo_evaluate(self._h, C.byref(prob), inst, _ptr(x), ld, n, _ptr(err),
                                           precision, _stream(stream)))
 
-    def evaluate_batch(self, items, precision=FP32, stream=None):
-        """items: list of (prob, inst, x, err[, n, ld])."""
+    @staticmethod
+    def prepare_batch(items):
+        """Marshal a list of (prob, inst, x, err[, n, ld]) once; the result can
+        be passed to evaluate_batch any number of times."""
         arr = (EvalItem * len(items))()
         for k, it in enumerate(items):
             prob, inst, x, err = it[:4]
             n = it[4] if len(it) > 4 else x.shape[1]
             ld = it[5] if len(it) > 5 else x.stride(0)
             arr[k] = EvalItem(prob, inst, n, ld, _ptr(x), _ptr(err))
-        self._check(self._L.sevo_evaluate_batch(self._h, arr, len(items), precision, _stream(stream)))
+        return arr
+
+    def evaluate_batch(self, items, precision=FP32, stream=None):
+        """items: list of (prob, inst, x, err[, n, ld]) or a prepare_batch() result."""
+        arr = items if isinstance(items, C.Array) else self.prepare_batch(items)
+        self._check(self._L.sevo_evaluate_batch(self._h, arr, len(arr), precision, _stream(stream)))
 
     def de_step(self, prob, inst, state: DEState, F, CR, precision=FP32, stream=None):
         self._check(self._L.sevo_de_step(self._h, C.byref(prob), inst, C.byref(state),
