@@ -151,6 +151,8 @@ struct sevo_ctx {
     Consts consts;
     int tiles_per_block = 0;     // 0 = automatic
     sevo::Workspace ws;
+    std::vector<hipStream_t> streams;   // internal, default priority
+    std::vector<hipEvent_t> fork_ev;    // one per internal stream + the fork event
 };
 
 static std::string g_create_error;
@@ -287,28 +289,17 @@ int get_instance(sevo_ctx *ctx, const sevo_problem *p, uint32_t inst, DevInstanc
     return SEVO_OK;
 }
 
-// Stage a descriptor table (item descriptors followed by the logical block
-// -> item map) in device memory.  Slots rotate; a slot is rewritten only
-// after the kernels that read it have finished.  A table equal to the
-// previous call's is reused in place (read-only), with no copy.
-int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t stream,
-                const EvalDesc **d_out, int *slot_out)
+// Stage bytes in device memory.  Slots rotate; a slot is rewritten only
+// after the kernels that read it have finished.  Content equal to a slot that
+// is still valid is reused in place (read-only), with no copy.
+int stage_bytes(sevo_ctx *ctx, const std::vector<char> &blob, hipStream_t stream, const void **d_out,
+                int *slot_out)
 {
-    std::vector<char> blob(descs.size() * sizeof(EvalDesc));
-    std::memcpy(blob.data(), descs.data(), blob.size());
-    int total = 0;
-    for (const auto &d : descs) total = std::max(total, d.block0 + d.nblocks);
-    std::vector<int32_t> map(total, 0);
-    for (size_t i = 0; i < descs.size(); ++i)
-        for (int b = 0; b < descs[i].nblocks; ++b) map[descs[i].block0 + b] = (int32_t)i;
-    const size_t off = blob.size();
-    blob.resize(off + map.size() * sizeof(int32_t));
-    if (!map.empty()) std::memcpy(blob.data() + off, map.data(), map.size() * sizeof(int32_t));
     const size_t n = blob.size();
-    for (int k = 0; k < (int)ctx->slots.size() && ctx->last_slot >= 0; ++k) {
+    for (int k = 0; k < (int)ctx->slots.size(); ++k) {
         DescSlot &s = ctx->slots[k];
         if (s.used == n && s.valid && std::memcmp(s.h, blob.data(), n) == 0) {
-            *d_out = reinterpret_cast<const EvalDesc *>(s.d);
+            *d_out = s.d;
             *slot_out = k;
             return SEVO_OK;
         }
@@ -331,13 +322,33 @@ int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t s
     s.used = n;
     HIP_TRY(ctx, hipMemcpyAsync(s.d, s.h, n, hipMemcpyHostToDevice, stream));
     s.valid = true;
-    ctx->last_slot = idx;
-    *d_out = reinterpret_cast<const EvalDesc *>(s.d);
+    *d_out = s.d;
     *slot_out = idx;
     return SEVO_OK;
 }
 
-int finish_slot(sevo_ctx *ctx, int slot, hipStream_t stream)
+// Stage an evaluation table: item descriptors followed by the logical block
+// -> item map.
+int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t stream,
+                const EvalDesc **d_out, int *slot_out)
+{
+    std::vector<char> blob(descs.size() * sizeof(EvalDesc));
+    std::memcpy(blob.data(), descs.data(), blob.size());
+    int total = 0;
+    for (const auto &d : descs) total = std::max(total, d.block0 + d.nblocks);
+    std::vector<int32_t> map(total, 0);
+    for (size_t i = 0; i < descs.size(); ++i)
+        for (int b = 0; b < descs[i].nblocks; ++b) map[descs[i].block0 + b] = (int32_t)i;
+    const size_t off = blob.size();
+    blob.resize(off + map.size() * sizeof(int32_t));
+    if (!map.empty()) std::memcpy(blob.data() + off, map.data(), map.size() * sizeof(int32_t));
+    const void *d = nullptr;
+    int rc = stage_bytes(ctx, blob, stream, &d, slot_out);
+    *d_out = reinterpret_cast<const EvalDesc *>(d);
+    return rc;
+}
+
+int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
 {
     HIP_TRY(ctx, hipEventRecord(ctx->slots[slot].done, stream));
     return SEVO_OK;
@@ -389,7 +400,7 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
         int rc = stage_descs(ctx, v, stream, &dd, &slot);
         if (rc) return rc;
         HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), ks, blocks, tpb, ctx->consts, stream));
-        if ((rc = finish_slot(ctx, slot, stream))) return rc;
+        if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     }
     if (!f64.empty()) {
         int blocks = 0;
@@ -403,7 +414,7 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
         int rc = stage_descs(ctx, f64, stream, &dd, &slot);
         if (rc) return rc;
         HIP_TRY(ctx, launch_eval_f64(dd, (int)f64.size(), blocks, ctx->consts, stream));
-        if ((rc = finish_slot(ctx, slot, stream))) return rc;
+        if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     }
     if (!large.empty()) {
         int rc = eval_large(ctx, large, precision == SEVO_SPLIT_BF16, stream);
@@ -438,7 +449,7 @@ int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStre
     int slot;
     if ((rc = stage_descs(ctx, v, stream, &dd, &slot))) return rc;
     HIP_TRY(ctx, launch_eval_large(dd, (int)v.size(), blocks, bf16, ctx->consts, stream));
-    if ((rc = finish_slot(ctx, slot, stream))) return rc;
+    if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     // combine: one thread per point, blocks of 256 points
     std::vector<EvalDesc> c = v;
     for (auto &d : c) {
@@ -448,7 +459,7 @@ int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStre
     }
     if ((rc = stage_descs(ctx, c, stream, &dd, &slot))) return rc;
     HIP_TRY(ctx, launch_eval_large_combine(dd, (int)c.size(), cblocks, ctx->consts, stream));
-    if ((rc = finish_slot(ctx, slot, stream))) return rc;
+    if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     return SEVO_OK;
 }
 
@@ -498,6 +509,58 @@ int sevo::lookup_instance(sevo_ctx *ctx, const sevo_problem *p, uint32_t inst, I
     out->tab = I->d_tab;
     out->Mbf = I->d_Mbf;
     return SEVO_OK;
+}
+
+int sevo::stage_blob(sevo_ctx *ctx, const std::vector<char> &blob, hipStream_t stream,
+                     const void **d_out, int *slot_out)
+{
+    return stage_bytes(ctx, blob, stream, d_out, slot_out);
+}
+
+int sevo::finish_slot(sevo_ctx *ctx, int slot, hipStream_t stream)
+{
+    return finish_slot_impl(ctx, slot, stream);
+}
+
+int sevo::fork_streams(sevo_ctx *ctx, hipStream_t parent, int n, hipStream_t *out)
+{
+    while ((int)ctx->streams.size() < n) {
+        hipStream_t s;
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        ctx->streams.push_back(s);
+    }
+    while ((int)ctx->fork_ev.size() < n + 1) {
+        hipEvent_t e;
+        HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->fork_ev.push_back(e);
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->fork_ev[n], parent));
+    for (int k = 0; k < n; ++k) {
+        HIP_TRY(ctx, hipStreamWaitEvent(ctx->streams[k], ctx->fork_ev[n], 0));
+        out[k] = ctx->streams[k];
+    }
+    return SEVO_OK;
+}
+
+int sevo::join_streams(sevo_ctx *ctx, hipStream_t parent, int n, const hipStream_t *streams)
+{
+    for (int k = 0; k < n; ++k) {
+        HIP_TRY(ctx, hipEventRecord(ctx->fork_ev[k], streams[k]));
+        HIP_TRY(ctx, hipStreamWaitEvent(parent, ctx->fork_ev[k], 0));
+    }
+    return SEVO_OK;
+}
+
+sevo::DeviceScope::DeviceScope(sevo_ctx *ctx)
+{
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
+}
+
+sevo::DeviceScope::~DeviceScope()
+{
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
 }
 
 const Consts &sevo::ctx_consts(sevo_ctx *ctx) { return ctx->consts; }
@@ -556,6 +619,8 @@ int sevo_destroy(sevo_ctx *ctx)
         }
         ctx->ws.release();
         sevo::release_state(ctx);
+        for (auto s : ctx->streams) (void)hipStreamDestroy(s);
+        for (auto e : ctx->fork_ev) (void)hipEventDestroy(e);
     }
     delete ctx;
     return SEVO_OK;

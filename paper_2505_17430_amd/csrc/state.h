@@ -34,6 +34,24 @@ struct InstanceView {
 };
 
 int set_error(sevo_ctx *ctx, int code, const char *msg);
+
+// Makes the context's GPU current for the scope of a call.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(sevo_ctx *ctx);
+    ~DeviceScope();
+};
+
+// Stage bytes in device memory on `stream` (content-cached, see runtime.hip);
+// finish_slot records that the kernels reading the slot are queued.
+int stage_blob(sevo_ctx *ctx, const std::vector<char> &blob, hipStream_t stream, const void **d_out,
+               int *slot_out);
+int finish_slot(sevo_ctx *ctx, int slot, hipStream_t stream);
+
+// Fork `n` internal streams off `parent` (each waits for the work queued on
+// parent so far) and join them back (parent waits for all of them).
+int fork_streams(sevo_ctx *ctx, hipStream_t parent, int n, hipStream_t *out);
+int join_streams(sevo_ctx *ctx, hipStream_t parent, int n, const hipStream_t *streams);
 int lookup_instance(sevo_ctx *ctx, const sevo_problem *p, uint32_t inst, InstanceView *out);
 const Consts &ctx_consts(sevo_ctx *ctx);
 uint32_t ctx_seed32(sevo_ctx *ctx);
@@ -43,5 +61,10 @@ void release_state(sevo_ctx *ctx);
 int eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items, int precision,
                hipStream_t stream);
 int eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStream_t stream);
+
+// Plain double-precision runs (steps.hip): one run at a time, one launch per
+// generation step.
+int run_plain_f64(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *results,
+                  float *trace, int64_t trace_len, double *best_x, int max_dim, hipStream_t stream);
 
 }  // namespace sevo

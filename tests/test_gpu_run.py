@@ -1,0 +1,195 @@
+"""GPU parity of whole runs (sevo_run) against the FP64 oracle.
+
+* FP64 plain path (one run per launch sequence): the same Philox stream and
+  double arithmetic as the oracle, so whole DE / PSO trajectories agree:
+  evaluations and generations exactly, the best error and every trace entry
+  to a relative 1e-9.
+* FP32 fused path: FE accounting and generation counts exactly; the
+  initial population's best exactly (its point bit for bit); the recorder's
+  invariants; the final error re-checked in double; and, since single
+  precision legitimately leaves the double trajectory after the first
+  generations, the distribution of final errors over many runs against the
+  oracle's (two-sample KS), for DE, PSO and SHADE.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+from paper_2505_17430_amd import sevo as S  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+SEED, ISEED = W.BASE_SEED, W.INSTANCE_SEED
+LB, UB = W.LB, W.UB
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = S.Context(0, SEED, ISEED)
+    yield c
+    c.close()
+
+
+def desc(algo, func, dim, np_, budget, uid, inst=0, **kw):
+    d = dict(F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618, vmax=0.2 * (UB - LB), p=0.1, H=6)
+    d.update(kw)
+    return S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, d["F"], d["CR"], d["w"],
+                     d["c1"], d["c2"], d["vmax"], d["p"], d["H"])
+
+
+def odesc(d):
+    return dict(algo=d.algo, func=d.prob.func, dim=d.prob.dim, lb=d.prob.lb, ub=d.prob.ub,
+                instance=d.instance, run_uid=d.run_uid, np=d.np, budget=d.budget, F=d.F, CR=d.CR,
+                w=d.w, c1=d.c1, c2=d.c2, vmax=d.vmax, p=d.p, H=d.H)
+
+
+def gpu_run(ctx, descs, precision=S.FP32, trace_len=0, max_dim=None):
+    n = len(descs)
+    max_dim = max_dim or max(d.prob.dim for d in descs)
+    res = torch.zeros((n, 32), dtype=torch.uint8, device="cuda")
+    tr = torch.full((max(n * trace_len, 1),), -7.0, device="cuda")
+    bx = torch.zeros((n, max_dim), dtype=torch.float64, device="cuda")
+    say(f"  run n={n} prec={precision} algos={sorted(set(d.algo for d in descs))}")
+    ctx.run(descs, res, tr if trace_len else None, trace_len, bx, max_dim, precision=precision)
+    torch.cuda.synchronize()
+    raw = res.cpu().numpy().tobytes()
+    out = []
+    for r in range(n):
+        rr = S.RunResult.from_buffer_copy(raw[r * 32:(r + 1) * 32])
+        out.append(dict(best_e=rr.best_e, best_e32=rr.best_e32, success=rr.success, fes=rr.fes,
+                        generations=rr.generations))
+    return out, tr.cpu().numpy()[: n * trace_len].reshape(n, trace_len), bx.cpu().numpy()
+
+
+def test_result_struct_size():
+    import ctypes
+    assert ctypes.sizeof(S.RunResult) == 32
+
+
+@pytest.mark.parametrize("algo,func,dim,np_,budget", [
+    (S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001),       # the plain DE configuration
+    (S.ALGO_DE, S.ROSENBROCK, 5, 20, 4000),
+    (S.ALGO_PSO, S.GRIEWANK, 10, 40, 40 * 201),
+    (S.ALGO_PSO, S.SCHWEFEL, 4, 7, 1000),
+])
+def test_fp64_plain_path_matches_oracle_trajectory(ctx, algo, func, dim, np_, budget):
+    d = desc(algo, func, dim, np_, budget, uid=11)
+    tl = budget // 200
+    (g,), tr, bx = gpu_run(ctx, [d], precision=S.FP64, trace_len=tl)
+    o, otr, obx = O.run(odesc(d), SEED, ISEED, trace_len=tl)
+    say(f"  fp64 gpu best={g['best_e']:.6e} oracle best={o['best_e']:.6e}")
+    assert g["fes"] == o["fes"] and g["generations"] == o["generations"]
+    assert g["best_e"] == pytest.approx(o["best_e"], rel=1e-9, abs=1e-13)
+    assert np.allclose(tr[0], otr, rtol=1e-6, atol=1e-12)
+    assert np.allclose(bx[0, :dim], obx, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("algo", [S.ALGO_DE, S.ALGO_PSO, S.ALGO_SHADE])
+def test_fused_init_only(ctx, algo):
+    """Budget = NP: only the initial population is evaluated."""
+    func, dim, np_ = S.ACKLEY, 30, 50
+    d = desc(algo, func, dim, np_, np_, uid=21)
+    (g,), _, bx = gpu_run(ctx, [d])
+    X = O.init_population(func, dim, LB, UB, np_, 21, SEED).astype(np.float32).astype(np.float64)
+    o, M = O.instance(func, dim, 0, ISEED)
+    e = O.errors(func, o, M, X)
+    assert g["fes"] == np_ and g["generations"] == 0
+    assert g["best_e32"] == pytest.approx(e.min(), rel=1e-5)
+    i = int(np.argmin(e))
+    if np.sort(e)[1] - e.min() > 1e-4 * e.min():
+        assert np.array_equal(bx[0, :dim], X[i])
+
+
+@pytest.mark.parametrize("algo,np_,budget", [(S.ALGO_DE, 50, 50 * 11 + 3), (S.ALGO_PSO, 40, 40 * 7),
+                                             (S.ALGO_SHADE, 180, 180 * 5 - 1)])
+def test_fused_fe_accounting_and_trace(ctx, algo, np_, budget):
+    d = desc(algo, S.RASTRIGIN, 10, np_, budget, uid=31)
+    tl = budget // 200 + 2
+    (g,), tr, _ = gpu_run(ctx, [d], trace_len=tl)
+    o, _, _ = O.run(odesc(d), SEED, ISEED, trace_len=0)
+    assert g["fes"] == o["fes"] and g["generations"] == o["generations"]
+    n_rec = g["fes"] // 200
+    t = tr[0]
+    assert np.all(np.isfinite(t[:min(n_rec, tl)]))
+    assert np.all(t[min(n_rec, tl):] == -7.0)        # entries past the run are untouched
+    assert np.all(np.diff(t[:min(n_rec, tl)]) <= 0)
+    assert g["best_e32"] <= t[0]
+    assert g["best_e"] == pytest.approx(g["best_e32"], rel=1e-5, abs=1e-6)
+
+
+def test_fused_matches_step_api_first_generation(ctx):
+    """Budget 2 NP: init + one DE generation; the fused kernel's best equals
+    the best of the unfused step kernels' initial and trial errors."""
+    func, dim, np_ = S.GRIEWANK, 10, 24
+    d = desc(S.ALGO_DE, func, dim, np_, 2 * np_, uid=41)
+    (g,), _, _ = gpu_run(ctx, [d])
+    ld = np_
+    x = torch.zeros(dim * ld, device="cuda"); u = torch.zeros_like(x)
+    ex = torch.zeros(ld, device="cuda"); eu = torch.zeros_like(ex)
+    for t in (0, 1):
+        st = S.DEState(1, np_, ld, dim * ld, 41, t, x.data_ptr(), ex.data_ptr(), u.data_ptr(),
+                       eu.data_ptr(), 0, 0)
+        if t == 1:
+            e0 = ex.cpu().numpy().copy()
+        ctx.de_step(S.problem(func, dim), 0, st, 0.5, 0.9)
+    torch.cuda.synchronize()
+    best = min(e0.min(), eu.cpu().numpy().min())
+    assert g["best_e32"] == pytest.approx(best, rel=2e-5, abs=1e-6)
+
+
+def _dist_compare(ctx, algo, func, dim, np_, budget, n, **kw):
+    descs = [desc(algo, func, dim, np_, budget, uid=1000 + r, inst=r % 3, **kw) for r in range(n)]
+    gres, _, _ = gpu_run(ctx, descs)
+    ores = [O.run(odesc(d), SEED, ISEED)[0] for d in descs]
+    for g, o in zip(gres, ores):
+        assert g["fes"] == o["fes"] and g["generations"] == o["generations"]
+    ge = np.array([g["best_e"] for g in gres])
+    oe = np.array([o["best_e"] for o in ores])
+    p = stats.ks_2samp(np.log10(ge + 1e-12), np.log10(oe + 1e-12)).pvalue
+    say(f"  median gpu {np.median(ge):.3e} oracle {np.median(oe):.3e} KS p={p:.3g}")
+    assert p > 1e-3
+    return ge, oe
+
+
+def test_fused_de_distribution(ctx):
+    _dist_compare(ctx, S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 301, 48)
+
+
+def test_fused_pso_distribution(ctx):
+    _dist_compare(ctx, S.ALGO_PSO, S.ELLIPSOID, 10, 40, 40 * 301, 48)
+
+
+def test_fused_shade_distribution(ctx):
+    _dist_compare(ctx, S.ALGO_SHADE, S.ROSENBROCK, 10, 100, 100 * 151, 32)
+
+
+def test_fused_mixed_batch_matches_single_runs(ctx):
+    """Runs of different algorithms and dimensions in one call give the same
+    results as the same runs alone (no cross-run interference)."""
+    descs = [desc(S.ALGO_DE, S.RASTRIGIN, 10, 20, 2000, uid=5),
+             desc(S.ALGO_PSO, S.ACKLEY, 30, 40, 2400, uid=6),
+             desc(S.ALGO_SHADE, S.SCHWEFEL, 50, 60, 3000, uid=7),
+             desc(S.ALGO_DE, S.ELLIPSOID, 100, 32, 1000, uid=8)]
+    batch, _, bxb = gpu_run(ctx, descs, max_dim=100)
+    for k, d in enumerate(descs):
+        (one,), _, bx1 = gpu_run(ctx, [d], max_dim=100)
+        assert one == batch[k]
+        assert np.array_equal(bx1[0], bxb[k])
+
+
+def test_run_rejects_bad_arguments(ctx):
+    res = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_DE, 0, 10, 3, 100, 1)], res)             # NP < 4
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_SHADE, 0, 10, 20, 100, 1, H=0)], res)    # H = 0
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_DE, 0, 10, 300, 1000, 1)], res)          # NP > 256
