@@ -29,12 +29,16 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     return x * q + (x < r ? x : r) + k;
 }
 
-// One workgroup = 4 waves; each wave owns 16*CT points of a tile of 64*CT
-// points and walks `tpb` consecutive tiles of one item, loading the next
-// tile's coordinates while the current one is rotated and reduced.
+// Persistent grid: the tiles (64*CT points each) of all items of one call are
+// numbered consecutively, item after item; workgroup L walks the contiguous
+// range [L T / G, (L + 1) T / G).  The rotation of an item is staged in LDS
+// when the walk enters the item, and each wave loads the coordinates of its
+// next tile while the current one is rotated and reduced.  Logical
+// workgroups are renumbered per XCD, so an XCD works through a contiguous
+// stretch of items and their rotations stay in that XCD's L2.
 template <int KS, int CT>
-__global__ __launch_bounds__(256) void k_eval_small(const EvalDesc *__restrict__ items, int n_items,
-                                                    int total_blocks, int tpb, Consts K)
+__global__ __launch_bounds__(256, 3) void k_eval_small(const EvalDesc *__restrict__ items, int n_items,
+                                                    int total_tiles, int grid, Consts K)
 {
     constexpr int RT = (KS + 3) / 4;
     constexpr int TILE = 64 * CT;
@@ -42,38 +46,50 @@ __global__ __launch_bounds__(256) void k_eval_small(const EvalDesc *__restrict__
     __shared__ double sO[KS * 4];
     __shared__ float sT[RT * 16];
 
-    const int L = xcd_remap(blockIdx.x, total_blocks);
-    const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
-    const int dim = it.dim, n = it.n, func = it.func;
-    const int64_t ld = it.ld;
-
-    const SEVO_GLOBAL float *Mg = gin<float>(it.Mfrag);
-    const SEVO_GLOBAL double *og = gin<double>(it.o);
-    const SEVO_GLOBAL float *tg = gin<float>(it.tab);
-    for (int q = threadIdx.x; q < RT * KS * 64; q += 256) sA[q] = Mg[q];
-    for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < dim ? og[q] : 0.0;
-    for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
-    __syncthreads();
-
+    const int L = xcd_remap(blockIdx.x, grid);
+    const int tb = (int)(((int64_t)L * total_tiles) / grid);
+    const int te = (int)(((int64_t)(L + 1) * total_tiles) / grid);
+    if (tb >= te) return;
+    const int32_t *__restrict__ tile_item = reinterpret_cast<const int32_t *>(items + n_items);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, pc = lane & 15;
-    const SEVO_GLOBAL float *__restrict__ X = gin<float>(it.x);
-    SEVO_GLOBAL float *__restrict__ E = gout<float>(it.err);
-    const int ntiles = (n + TILE - 1) / TILE;
-    const int t0 = (L - it.block0) * tpb;
-    const int t1 = min(t0 + tpb, ntiles);
-    if (t0 >= t1) return;
 
+    int cur = -1;
+    const EvalDesc *it = nullptr;
     float b[KS][CT], bn[KS][CT];
-    load_b<KS, CT>(bn, X, ld, dim, n, t0 * TILE + wave * 16 * CT, kq, pc, sO);
-    for (int tile = t0; tile < t1; ++tile) {
-        const int p0 = tile * TILE + wave * 16 * CT;
+    bool have_next = false;
+    for (int g = tb; g < te; ++g) {
+        const int item = tile_item[g];
+        if (item != cur) {
+            __syncthreads();   // every wave is done with the previous item's LDS
+            cur = item;
+            it = items + item;
+            const SEVO_GLOBAL float *Mg = gin<float>(it->Mfrag);
+            const SEVO_GLOBAL double *og = gin<double>(it->o);
+            const SEVO_GLOBAL float *tg = gin<float>(it->tab);
+#pragma unroll 8
+            for (int q = threadIdx.x; q < RT * KS * 64; q += 256) sA[q] = Mg[q];
+            for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
+            for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
+            __syncthreads();
+            have_next = false;
+        }
+        const int dim = it->dim, n = it->n;
+        const int64_t ld = it->ld;
+        const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
+        SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
+        const int p0 = (g - it->block0) * TILE + wave * 16 * CT;
+        if (have_next) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
+            for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) b[ks][c] = bn[ks][c];
-        if (tile + 1 < t1) load_b<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc, sO);
-        switch (func) {
+                for (int c = 0; c < CT; ++c) b[ks][c] = bn[ks][c];
+        } else {
+            load_b<KS, CT>(b, X, ld, dim, n, p0, kq, pc, sO);
+        }
+        have_next = g + 1 < te && tile_item[g + 1] == item;
+        if (have_next) load_b<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc, sO);
+        switch (it->func) {
         case ELLIPSOID: tile_body<ELLIPSOID, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
         case ROSENBROCK: tile_body<ROSENBROCK, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
         case RASTRIGIN: tile_body<RASTRIGIN, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
@@ -89,13 +105,6 @@ __global__ __launch_bounds__(256) void k_eval_small(const EvalDesc *__restrict__
 constexpr int ct_for(int ks) { return ks <= 8 ? 2 : 1; }
 
 int small_tile_points(int ks) { return 64 * ct_for(ks); }
-
-int small_blocks_for(int n, int ks, int tiles_per_block)
-{
-    const int tp = small_tile_points(ks);
-    const int ntiles = (n + tp - 1) / tp;
-    return (ntiles + tiles_per_block - 1) / tiles_per_block;
-}
 
 typedef void (*SmallKernel)(const EvalDesc *, int, int, int, Consts);
 
@@ -117,14 +126,24 @@ static SmallKernel small_table(int ks)
     }
 }
 
-hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_blocks,
-                             int tiles_per_block, const Consts &k, hipStream_t s)
+int small_resident_blocks(int ks)
+{
+    SmallKernel k = small_table(ks);
+    if (!k) return 1;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return per_cu * cus;
+}
+
+hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_tiles, int grid,
+                             const Consts &k, hipStream_t s)
 {
     SmallKernel kern = small_table(ks);
     if (!kern) return hipErrorInvalidValue;
-    if (total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(total_blocks), dim3(256), 0, s, d_items, n_items, total_blocks,
-                       tiles_per_block, k);
+    if (total_tiles <= 0 || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, d_items, n_items, total_tiles, grid, k);
     return hipGetLastError();
 }
 

@@ -145,11 +145,13 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         __syncthreads();
         if (threadIdx.x < KC) sO[threadIdx.x] = (k0 + (int)threadIdx.x < dim) ? og[k0 + threadIdx.x] : 0.0;
         __syncthreads();
+#pragma unroll 4
         for (int idx = threadIdx.x; idx < KC * PT; idx += 256) {
             const int kk = idx / PT, p = idx % PT;
             const int k = k0 + kk, pg = p_base + p;
-            float v = 0.f;
-            if (k < dim && pg < n) v = (float)((double)X[(int64_t)k * ld + pg] - sO[kk]);
+            // unconditional load from a clamped address, masked afterwards
+            const float raw = X[(int64_t)min(k, dim - 1) * ld + min(pg, n - 1)];
+            const float v = (k < dim && pg < n) ? (float)((double)raw - sO[kk]) : 0.f;
             if constexpr (!BF16) {
                 sB[kk * SB + p] = v;
             } else {

@@ -161,6 +161,7 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
     const int D = R.dim, np = R.np, npp = R.npp;
     const bool pso = R.algo == SEVO_ALGO_PSO, shade = R.algo == SEVO_ALGO_SHADE;
 
+#pragma unroll 8
     for (int q = tid; q < RT * KS * 64; q += 256) sA[q] = R.Mfrag[q];
     for (int q = tid; q < KS * 4; q += 256) sO[q] = q < D ? R.o[q] : 0.0;
     for (int q = tid; q < RT * 16; q += 256) sT[q] = R.tab[q];

@@ -62,10 +62,12 @@ inline int rt_of(int dim) { return (dim + 15) / 16; }
 inline int ks32_of(int dim) { return (dim + 31) / 32; }
 
 // eval.hip
-int small_tile_points(int ks);            // points per workgroup iteration
-int small_blocks_for(int n, int ks, int tiles_per_block);
-hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_blocks,
-                             int tiles_per_block, const Consts &k, hipStream_t s);
+int small_tile_points(int ks);            // points per workgroup tile
+int small_resident_blocks(int ks);        // workgroups the whole GPU holds at once
+// d_items: descriptors (block0 = first tile, nblocks = tiles of the item)
+// followed by the tile -> item map.
+hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_tiles, int grid,
+                             const Consts &k, hipStream_t s);
 
 constexpr int LARGE_ROWS = 128;          // rows of z per workgroup (4 waves x 32)
 constexpr int LARGE_POINTS = 128;        // points per workgroup

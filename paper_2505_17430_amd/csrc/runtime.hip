@@ -354,11 +354,17 @@ int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
     return SEVO_OK;
 }
 
-int auto_tpb(sevo_ctx *ctx, long total_tiles)
+// Workgroups of a persistent small-D launch: as many as the GPU holds at
+// once (times SEVO_TILES_PER_BLOCK^-1 when that override is set, for tuning),
+// never more than there are tiles.
+int small_grid(sevo_ctx *ctx, int ks, int tiles)
 {
-    if (ctx->tiles_per_block > 0) return ctx->tiles_per_block;
-    long t = total_tiles / 2048;
-    return (int)std::min<long>(8, std::max<long>(1, t));
+    static std::map<int, int> resident;
+    auto itr = resident.find(ks);
+    if (itr == resident.end()) itr = resident.emplace(ks, small_resident_blocks(ks)).first;
+    long g = itr->second;
+    if (ctx->tiles_per_block > 0) g = (tiles + ctx->tiles_per_block - 1) / ctx->tiles_per_block;
+    return (int)std::max<long>(1, std::min<long>(g, tiles));
 }
 
 }  // namespace
@@ -386,20 +392,18 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
     for (auto &kv : small) {
         std::vector<EvalDesc> &v = kv.second;
         const int ks = kv.first, tp = small_tile_points(ks);
-        long tiles = 0;
-        for (auto &d : v) tiles += (d.n + tp - 1) / tp;
-        const int tpb = auto_tpb(ctx, tiles);
-        int blocks = 0;
+        int tiles = 0;
         for (auto &d : v) {
-            d.block0 = blocks;
-            d.nblocks = small_blocks_for(d.n, ks, tpb);
-            blocks += d.nblocks;
+            d.block0 = tiles;                       // first tile of the item
+            d.nblocks = (d.n + tp - 1) / tp;        // tiles of the item
+            tiles += d.nblocks;
         }
+        int grid = small_grid(ctx, ks, tiles);
         const EvalDesc *dd;
         int slot;
         int rc = stage_descs(ctx, v, stream, &dd, &slot);
         if (rc) return rc;
-        HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), ks, blocks, tpb, ctx->consts, stream));
+        HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), ks, tiles, grid, ctx->consts, stream));
         if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     }
     if (!f64.empty()) {

@@ -101,6 +101,19 @@ __device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL flo
                                        int64_t ld, int dim, int n, int p0, int kq, int pc,
                                        const double *sO)
 {
+    // Loads are unconditional, from a clamped (always valid) address, and the
+    // value is masked afterwards: a load under a per-lane branch would be
+    // waited for before the next one is issued.
+    float raw[KS][CT];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = min(ks * 4 + kq, dim - 1);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int p = min(p0 + c * 16 + pc, n - 1);
+            raw[ks][c] = X[(int64_t)k * ld + p];
+        }
+    }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k = ks * 4 + kq;
@@ -108,9 +121,7 @@ __device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL flo
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int p = p0 + c * 16 + pc;
-            float v = 0.f;
-            if (k < dim && p < n) v = (float)((double)X[(int64_t)k * ld + p] - ok);
-            b[ks][c] = v;
+            b[ks][c] = (k < dim && p < n) ? (float)((double)raw[ks][c] - ok) : 0.f;
         }
     }
 }
