@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
+                         "c4: batched SHADE; c5: D=1000 evaluation")
     return ap.parse_args()
 
 
@@ -63,21 +66,30 @@ def cpu_baseline(target_s):
         O.errors_soa_f32(f, o, M, X)
         return X.shape[1]
 
-    # calibrate on 4 points per group, then scale the sample to ~target_s
-    per = 4
+    # calibrate on a few points per group, then scale the sample to ~target_s
+    # (capped at the full 5100 points per group, repeating the full sweep
+    # when even that is shorter than the target)
+    per = 16
     jobs = [(f, d, k, W.uniform_points(W.group_seed(f, d, k, 1), d, per)) for (f, d, k, _) in groups]
     with cf.ThreadPoolExecutor(cores) as ex:
         t0 = time.perf_counter()
-        n = sum(ex.map(chunk, jobs))
+        sum(ex.map(chunk, jobs))
         dt = time.perf_counter() - t0
-        per = int(max(4, min(5100, per * target_s / max(dt, 1e-3))))
+        want = per * target_s / max(dt, 1e-4)
+        per = int(max(16, min(5100, want)))
         jobs = [(f, d, k, W.uniform_points(W.group_seed(f, d, k, 2), d, per)) for (f, d, k, _) in groups]
         t0 = time.perf_counter()
-        n = sum(ex.map(chunk, jobs))
+        n = 0
+        reps = 0
+        # whole passes over the sample until the target time is reached
+        while reps < 40 and (reps == 0 or time.perf_counter() - t0 < target_s):
+            n += sum(ex.map(chunk, jobs))
+            reps += 1
         dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{per} points per group x {len(groups)} groups (all 6 functions x "
-                      f"D in 10,30,50,100 x 10 instances), {n} evaluations, {dt:.1f} s"}
+            "sample": f"{reps} x {per} points per group x {len(groups)} groups (all 6 functions x "
+                      f"D in 10,30,50,100 x 10 instances, FP64 C oracle, threads over groups), "
+                      f"{n} evaluations in {dt:.1f} s"}
 
 
 def main():
@@ -86,6 +98,8 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
               f"(the runs shard with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if a.workload != "c2":
+        return run_workload(a)
     import torch
     from paper_2505_17430_amd import sevo as S
 
@@ -177,6 +191,180 @@ def main():
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Whole-run workloads (one line each; the default run measures only the
+# evaluation sweep above).
+
+def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
+    out = {"metric": metric, "value": round(value, 1), "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def _run_descs(S, specs):
+    """specs: list of (algo, func, dim, np, budget, instance, uid)."""
+    out = []
+    for (algo, func, dim, np_, budget, inst, uid) in specs:
+        out.append(S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, 0.7298,
+                             1.49618, 1.49618, 0.2 * (W.UB - W.LB), 0.1, 6))
+    return out
+
+
+def _time_runs(ctx, S, torch, descs, precision, steps, warmup, trace_len=0):
+    n = len(descs)
+    res = torch.zeros((n, 32), dtype=torch.uint8, device="cuda")
+    tr = torch.zeros(max(1, n * trace_len), device="cuda") if trace_len else None
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.run(descs, res, tr, trace_len, precision=precision, stream=st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        ctx.run(descs, res, tr, trace_len, precision=precision, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    raw = res.cpu().numpy().tobytes()
+    rr = [S.RunResult.from_buffer_copy(raw[32 * k: 32 * (k + 1)]) for k in range(n)]
+    return ms, rr
+
+
+def _oracle_runs(specs, seconds):
+    """The oracle on as many of the runs as fit ~seconds of host threads."""
+    import concurrent.futures as cf
+    import oracle as O
+    cores = len(os.sched_getaffinity(0))
+    keys = ["algo", "func", "dim", "np", "budget", "instance", "run_uid"]
+
+    def one(sp):
+        d = dict(zip(keys, sp))
+        d.update(lb=W.LB, ub=W.UB, F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618,
+                 vmax=0.2 * (W.UB - W.LB), p=0.1, H=6)
+        return O.run(d, W.BASE_SEED, W.INSTANCE_SEED)[0]["fes"]
+
+    t0 = time.perf_counter()
+    n = 0
+    done = 0
+    with cf.ThreadPoolExecutor(cores) as ex:
+        while time.perf_counter() - t0 < seconds and done < 50 * len(specs):
+            batch = [specs[(done + k) % len(specs)] for k in range(cores)]
+            n += sum(ex.map(one, batch))
+            done += len(batch)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} runs to completion (cycling over {len(specs)} of the workload's "
+                      f"runs), {n} evaluations in {dt:.1f} s"}
+
+
+def run_workload(a):
+    import torch
+    from paper_2505_17430_amd import sevo as S
+    ctx = S.Context(0, W.BASE_SEED, W.INSTANCE_SEED)
+    steps = max(1, min(a.steps, 5))
+    warm = 1
+    metric = "function evals/sec, batched FP32/split-BF16 vs plain FP64, at stated rel. error"
+    if a.workload == "c1":
+        spec = [(S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001, 0, 0)]
+        descs = _run_descs(S, spec)
+        ms64, r64 = _time_runs(ctx, S, torch, descs, S.FP64, steps, warm, trace_len=250)
+        ms32, r32 = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm, trace_len=250)
+        ev = r64[0].fes
+        extra = {"fused_fp32": {"evals_per_s": ev / (ms32 / 1e3), "ms": ms32,
+                                "best_e": r32[0].best_e},
+                 "plain_fp64": {"evals_per_s": ev / (ms64 / 1e3), "ms": ms64, "best_e": r64[0].best_e},
+                 "speedup_fused_vs_plain": ms64 / ms32}
+        if not a.no_cpu:
+            extra["cpu_baseline"] = _oracle_runs(spec, 10)
+        _line(metric, ev / (ms64 / 1e3), "evals/s", steps, warm, ms64,
+              {"workload": "plain DE rand/1/bin, one run: Rastrigin D=10, NP=50, F=0.5, CR=0.9, "
+                           "1000 generations, FP64 one-launch-per-step path"}, dtype="f64", **extra)
+    elif a.workload == "c3":
+        spec = []
+        for sw in range(4096):
+            f, d, k = W.c3_swarm(sw)
+            spec.append((S.ALGO_PSO, f, d, 40, 40 * 2001, k, sw))
+        descs = _run_descs(S, spec)
+        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm)
+        ev = sum(r.fes for r in rr)
+        # one swarm per launch: a sample of 24 swarms (8 per dimension), each its own call
+        sample = [descs[i] for i in range(0, 4096, 4096 // 24)][:24]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        res = torch.zeros((1, 32), dtype=torch.uint8, device="cuda")
+        st = torch.cuda.current_stream()
+        ctx.run(sample[:1], res, stream=st)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for d in sample:
+            ctx.run([d], res, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        per_swarm_ms = e0.elapsed_time(e1) / len(sample)
+        extra = {"one_swarm_per_launch": {"ms_per_swarm": per_swarm_ms,
+                                          "projected_ms_4096": per_swarm_ms * 4096,
+                                          "evals_per_s": (40 * 2001) / (per_swarm_ms / 1e3)},
+                 "speedup_batched_vs_per_launch": per_swarm_ms * 4096 / ms}
+        if not a.no_cpu:
+            extra["cpu_baseline"] = _oracle_runs(spec[::64], 10)
+        _line(metric, ev / (ms / 1e3), "evals/s", steps, warm, ms,
+              {"workload": "batched PSO: 4096 swarms x 40 particles, D in {10,30,50} x 6 functions x "
+                           "10 instances, 2000 iterations, one fused launch per dimension class",
+               "evals": ev}, **extra)
+    elif a.workload == "c4":
+        spec = []
+        for r in range(2048):
+            f, d, k, np_ = W.c4_run(r)
+            spec.append((S.ALGO_SHADE, f, d, np_, 10000 * d, k, r))
+        descs = _run_descs(S, spec)
+        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, 1, 0)
+        ev = sum(r.fes for r in rr)
+        succ = sum(r.success for r in rr)
+        extra = {"successes": succ}
+        if not a.no_cpu:
+            small = [sp for sp in spec if sp[2] == 10][:64]
+            extra["cpu_baseline"] = _oracle_runs(small, 10)
+        _line(metric, ev / (ms / 1e3), "evals/s", 1, 0, ms,
+              {"workload": "batched SHADE: 2048 runs, D in {10,30,50,100}, NP = min(18 D, 200), "
+                           "budget 10000 D, p = 0.1, H = 6", "evals": ev}, **extra)
+    elif a.workload == "c5":
+        out = {}
+        for prec, name in ((S.SPLIT_BF16, "split_bf16"), (S.FP32, "fp32")):
+            items = []
+            for f in (S.ELLIPSOID, S.RASTRIGIN):
+                x = torch.empty((1000, 6400), device="cuda").uniform_(W.LB, W.UB)
+                e = torch.empty(6400, device="cuda")
+                items.append((S.problem(f, 1000), 0, x, e))
+            batch = S.Context.prepare_batch(items)
+            st = torch.cuda.current_stream()
+            for _ in range(3):
+                ctx.evaluate_batch(batch, precision=prec, stream=st)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(st)
+            for _ in range(reps):
+                ctx.evaluate_batch(batch, precision=prec, stream=st)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            ev = 2 * 6400
+            fl = 2.0 * 1000 * 1000 * ev
+            out[name] = {"ms": ms, "evals_per_s": ev / (ms / 1e3),
+                         "tflops_fp32_equiv": fl / (ms / 1e3) / 1e12}
+        bf = out["split_bf16"]
+        roof = {"bound": "mfma", "achieved": round(3 * 2.0e6 * 12800 / (bf["ms"] / 1e3) / 1e12, 2),
+                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s", "traffic": None,
+                "note": "3 bf16 products per rotation flop; whole call (GEMM + combine)"}
+        roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+        _line(metric, bf["evals_per_s"], "evals/s", reps, 3, bf["ms"],
+              {"workload": "large scale: D=1000 Ellipsoid and Rastrigin, 64 runs x 100 points each, "
+                           "split-bf16 rotation on MFMA"}, dtype="bf16x3", precisions=out, roofline=roof)
+    ctx.close()
 
 
 if __name__ == "__main__":
