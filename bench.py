@@ -32,6 +32,38 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE counter
+# summary committed beside the kernel-trace summaries.  The figure is used
+# only while the kernel's sources hash to the value recorded with it.
+HBM_PROFILE = os.path.join(ROOT, "profiles", "k_eval_small_D100_hbm_counters.txt")
+KERNEL_SOURCES = ["eval.hip", "tile.h", "objective_f32.h", "runtime.h", "runtime.hip", "common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2505_17430_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the D=100 evaluation kernel, or None when the
+    counter summary is missing or was taken on other kernel sources."""
+    try:
+        with open(HBM_PROFILE) as f:
+            kv = dict(l.split(":", 1) for l in f if ":" in l and not l.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -42,9 +74,10 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
-                         "c4: batched SHADE; c5: D=1000 evaluation")
+                         "c4: batched SHADE; c5: D=1000 evaluation; copy: 512 MiB device copy "
+                         "(calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -82,7 +115,7 @@ def cpu_baseline(target_s):
         n = 0
         reps = 0
         # whole passes over the sample until the target time is reached
-        while reps < 40 and (reps == 0 or time.perf_counter() - t0 < target_s):
+        while reps < 400 and (reps == 0 or time.perf_counter() - t0 < target_s):
             n += sum(ex.map(chunk, jobs))
             reps += 1
         dt = time.perf_counter() - t0
@@ -96,7 +129,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              f"(the runs shard with no exchange; see the design notes)", file=sys.stderr)
+              f"(runs shard across GPUs with no exchange, so one GPU's share is the measured unit)", file=sys.stderr)
         sys.exit(2)
     if a.workload != "c2":
         return run_workload(a)
@@ -162,8 +195,12 @@ def main():
     else:   # small D runs the FP32 MFMA path in either precision
         achieved = flops100 / (d100_ms / 1e3) / 1e12
         peak = PEAK_FP32_MFMA_TFLOPS
+    traffic = measured_traffic()
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": None if traffic is None else int(traffic),
+            "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
+            "algorithmic_bytes": int(n100 * (4 * 100 + 4)),
             "kernel": "k_eval_small<25> (D=100 group: 60 items x 5100 points)",
             "kernel_ms": round(d100_ms, 4)}
     out = {
@@ -264,6 +301,15 @@ def _oracle_runs(specs, seconds):
 
 def run_workload(a):
     import torch
+    if a.workload == "copy":
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(a.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_read_per_copy": src.numel() * 4,
+                          "bytes_written_per_copy": src.numel() * 4, "copies": a.steps}), flush=True)
+        return
     from paper_2505_17430_amd import sevo as S
     ctx = S.Context(0, W.BASE_SEED, W.INSTANCE_SEED)
     steps = max(1, min(a.steps, 5))

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256, 3) void k_eval_small(const EvalDesc *__restric
 {
     constexpr int RT = (KS + 3) / 4;
     constexpr int TILE = 64 * CT;
-    __shared__ float sA[RT * KS * 64];
+    __shared__ __attribute__((aligned(16))) float sA[RT * KS * 64];
     __shared__ double sO[KS * 4];
     __shared__ float sT[RT * 16];
 
@@ -64,11 +64,9 @@ __global__ __launch_bounds__(256, 3) void k_eval_small(const EvalDesc *__restric
             __syncthreads();   // every wave is done with the previous item's LDS
             cur = item;
             it = items + item;
-            const SEVO_GLOBAL float *Mg = gin<float>(it->Mfrag);
             const SEVO_GLOBAL double *og = gin<double>(it->o);
             const SEVO_GLOBAL float *tg = gin<float>(it->tab);
-#pragma unroll 8
-            for (int q = threadIdx.x; q < RT * KS * 64; q += 256) sA[q] = Mg[q];
+            stage_rotation<KS>(sA, it->Mfrag);
             for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
             for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
             __syncthreads();

@@ -142,7 +142,7 @@ template <int KS>
 __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, uint32_t seed32, Consts K)
 {
     constexpr int RT = (KS + 3) / 4;
-    __shared__ float sA[RT * KS * 64];
+    __shared__ __attribute__((aligned(16))) float sA[RT * KS * 64];
     __shared__ double sO[KS * 4];
     __shared__ float sT[RT * 16];
     __shared__ unsigned long long sKey[256];
@@ -161,8 +161,7 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
     const int D = R.dim, np = R.np, npp = R.npp;
     const bool pso = R.algo == SEVO_ALGO_PSO, shade = R.algo == SEVO_ALGO_SHADE;
 
-#pragma unroll 8
-    for (int q = tid; q < RT * KS * 64; q += 256) sA[q] = R.Mfrag[q];
+    stage_rotation<KS>(sA, R.Mfrag);
     for (int q = tid; q < KS * 4; q += 256) sO[q] = q < D ? R.o[q] : 0.0;
     for (int q = tid; q < RT * 16; q += 256) sT[q] = R.tab[q];
     if (tid < 16) { sMF[tid] = 0.5f; sMCR[tid] = 0.5f; }

@@ -95,16 +95,16 @@ __device__ __forceinline__ void tile_body(const float (&b)[KS][CT], const float 
     }
 }
 
-// Load the shifted coordinates of one wave's 16*CT points (B operands).
+// Coordinates of one wave's 16*CT points, in two halves so a caller can
+// keep the loads of the next tile in flight while it computes the current
+// one: load_raw only issues the loads (unconditional, from a clamped and
+// therefore always valid address -- a load under a per-lane branch would be
+// waited for before the next one is issued); shift_raw then masks the
+// padding and applies the shift in double, rounding d = x - o once to float.
 template <int KS, int CT>
-__device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL float *__restrict__ X,
-                                       int64_t ld, int dim, int n, int p0, int kq, int pc,
-                                       const double *sO)
+__device__ __forceinline__ void load_raw(float (&raw)[KS][CT], const SEVO_GLOBAL float *__restrict__ X,
+                                         int64_t ld, int dim, int n, int p0, int kq, int pc)
 {
-    // Loads are unconditional, from a clamped (always valid) address, and the
-    // value is masked afterwards: a load under a per-lane branch would be
-    // waited for before the next one is issued.
-    float raw[KS][CT];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k = min(ks * 4 + kq, dim - 1);
@@ -114,6 +114,12 @@ __device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL flo
             raw[ks][c] = X[(int64_t)k * ld + p];
         }
     }
+}
+
+template <int KS, int CT>
+__device__ __forceinline__ void shift_raw(float (&b)[KS][CT], int dim, int n, int p0, int kq, int pc,
+                                          const double *sO)
+{
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k = ks * 4 + kq;
@@ -121,9 +127,39 @@ __device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL flo
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int p = p0 + c * 16 + pc;
-            b[ks][c] = (k < dim && p < n) ? (float)((double)raw[ks][c] - ok) : 0.f;
+            b[ks][c] = (k < dim && p < n) ? (float)((double)b[ks][c] - ok) : 0.f;
         }
     }
+}
+
+// Copy the rotation fragments (RT*KS*64 floats, a whole number of float4s,
+// 16-byte aligned) from global memory to LDS: every thread first issues all
+// of its float4 loads (unconditional, clamped index), then stores them.
+template <int KS>
+__device__ __forceinline__ void stage_rotation(float *sA, const float *Mfrag)
+{
+    constexpr int RT = (KS + 3) / 4;
+    constexpr int NV = RT * KS * 16;
+    constexpr int PER = (NV + 255) / 256;
+    const SEVO_GLOBAL floatx4 *M4 = reinterpret_cast<const SEVO_GLOBAL floatx4 *>(gin<float>(Mfrag));
+    floatx4 *s4 = reinterpret_cast<floatx4 *>(sA);
+    floatx4 tmp[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) tmp[k] = M4[min((int)threadIdx.x + k * 256, NV - 1)];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int q = threadIdx.x + k * 256;
+        if (q < NV) s4[q] = tmp[k];
+    }
+}
+
+template <int KS, int CT>
+__device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL float *__restrict__ X,
+                                       int64_t ld, int dim, int n, int p0, int kq, int pc,
+                                       const double *sO)
+{
+    load_raw<KS, CT>(b, X, ld, dim, n, p0, kq, pc);
+    shift_raw<KS, CT>(b, dim, n, p0, kq, pc, sO);
 }
 
 }  // namespace sevo
