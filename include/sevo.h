@@ -136,7 +136,7 @@ int sevo_set_instance(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance
 
 /* Errors of n points of one (problem, instance).
  *   x       device, [dim][ld] structure-of-arrays, float (FP32, SPLIT_BF16)
- *           or double (FP64); ld >= n.
+ *           or double (FP64); n <= ld <= 2^28.
  *   err_out device, [n], float or double like x: e = f(x) - f*.
  * n = 0 is a no-op.  Asynchronous on `stream`. */
 int sevo_evaluate(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
@@ -150,7 +150,7 @@ typedef struct {
     sevo_problem prob;
     uint32_t instance;
     int32_t n;
-    int64_t ld;
+    int64_t ld;           /* n <= ld <= 2^28 */
     const void *x;        /* device */
     void *err_out;        /* device */
 } sevo_eval_item;
@@ -170,7 +170,7 @@ int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_it
 typedef struct {
     int32_t n_runs;
     int32_t np;            /* population size, >= 4 */
-    int64_t ld;            /* >= np */
+    int64_t ld;            /* np <= ld <= 2^28 */
     int64_t run_stride;    /* >= dim * ld */
     uint32_t run_uid0;
     uint32_t generation;
@@ -200,7 +200,7 @@ int sevo_de_step(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance,
 typedef struct {
     int32_t n_runs;
     int32_t np;            /* swarm size, >= 1 */
-    int64_t ld;
+    int64_t ld;            /* np <= ld <= 2^28 */
     int64_t run_stride;
     uint32_t run_uid0;
     uint32_t iteration;    /* 0 initialises; t >= 1 makes iteration t */

@@ -9,8 +9,8 @@
 //    Q = 1 - prod (1 - y_i) obeys Q <- Q + y (1 - Q), exact in real
 //    arithmetic, free of cancellation near the optimum, and two partial Q
 //    combine with the same rule; its additions are compensated;
-//  - Schwefel branch-free: one sqrt of |u|, one sincos, and selects for the
-//    four regions of u = z + s;
+//  - Schwefel branch-free: one sqrt of |u|, one reciprocal, one sincos, and
+//    selects for the four regions of u = z + s;
 //  - compensation per group of four rows: the four terms of a 16-row MFMA
 //    tile that a lane holds are added plainly, then the group sum enters the
 //    lane's running sum through an error-free TwoSum.  All terms of a sum
@@ -88,20 +88,28 @@ __device__ __forceinline__ float schwefel_g_f32(float z, const SchwefelConst<flo
 {
     constexpr float INV_PI = 0.318309886183790671538f;
     const float u = K.s + z;
-    const float sq = __builtin_sqrtf(fabsf(u));
+    const float sq = __builtin_amdgcn_sqrtf(fabsf(u));   // hardware sqrt, about 1 ulp
     const bool pos = u > 0.f;
-    // u > 0: t = z / (sqrt s + sqrt u), angle t/2; u <= 0: angle sqrt|u|
-    const float theta = pos ? (0.5f * INV_PI) * (z / (K.a + sq)) : sq * INV_PI;
+    // u > 0: t = z / (sqrt s + sqrt u), angle t/2; u <= 0: angle sqrt|u|.
+    // The hardware reciprocal (about 1 ulp) replaces a correctly rounded
+    // division, which the compiler would otherwise put behind a branch.
+    const float th_pos = (0.5f * INV_PI) * (z * __builtin_amdgcn_rcpf(K.a + sq));
+    const float th_neg = sq * INV_PI;
+    const float theta = pos ? th_pos : th_neg;
     float sh, ch;
     sincos_pi(theta, sh, ch);
     const float sin_t = 2.f * sh * ch;
     const float cos_t = fmaf(-2.f * sh, sh, 1.f);
     const float cos_ah = K.ca * ch - K.sa * sh;
     const float sin_at = K.sa * cos_t + K.ca * sin_t;
-    float g = pos ? (-2.f * K.s) * cos_ah * sh - z * sin_at : K.c - u * sh;
+    const float g_pos = (-2.f * K.s) * cos_ah * sh - z * sin_at;
+    const float g_neg = K.c - u * sh;
     const float bh = z - K.zhi, bl = K.zlo - z;
-    g = (z > K.zhi) ? fmaf(K.lambda * bh, bh, K.gp) : g;
-    g = (z < K.zlo) ? fmaf(K.lambda * bl, bl, K.gm) : g;
+    const float g_hi = fmaf(K.lambda * bh, bh, K.gp);
+    const float g_lo = fmaf(K.lambda * bl, bl, K.gm);
+    float g = pos ? g_pos : g_neg;
+    g = (z > K.zhi) ? g_hi : g;
+    g = (z < K.zlo) ? g_lo : g;
     return g;
 }
 
@@ -114,29 +122,40 @@ __device__ __forceinline__ void add_group(AccF &a, const float z[4], float zn3, 
                                           bool has_next3, const float tab[4],
                                           const SchwefelConst<float> &K)
 {
+    // Every term is computed for all four rows and then selected, so that the
+    // fold is straight-line code (a conditional expression with a costly arm
+    // would become a branch) and can be scheduled between matrix-core ops.
     float g1 = 0.f, g2 = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const bool ok = j < valid;
         const float zj = z[j];
         if constexpr (FUNC == ELLIPSOID) {
-            g1 += ok ? tab[j] * zj * zj : 0.f;
+            const float t = tab[j] * zj * zj;
+            g1 += ok ? t : 0.f;
         } else if constexpr (FUNC == ROSENBROCK) {
             const float zn = j < 3 ? z[j < 3 ? j + 1 : 0] : zn3;
             const bool nx = j < 3 ? (j + 1 < valid) : has_next3;
             const float q = fmaf(zj, zj, 2.f * zj) - zn;
-            g1 += (ok && nx) ? fmaf(100.f * q, q, zj * zj) : 0.f;
+            const float t = fmaf(100.f * q, q, zj * zj);
+            g1 += (ok && nx) ? t : 0.f;
         } else if constexpr (FUNC == RASTRIGIN) {
-            g1 += ok ? fmaf(20.f, sin2_pi(zj), zj * zj) : 0.f;
+            const float t = fmaf(20.f, sin2_pi(zj), zj * zj);
+            g1 += ok ? t : 0.f;
         } else if constexpr (FUNC == SCHWEFEL) {
-            g1 += ok ? schwefel_g_f32(zj, K) : 0.f;
+            const float t = schwefel_g_f32(zj, K);
+            g1 += ok ? t : 0.f;
         } else if constexpr (FUNC == GRIEWANK) {
-            g1 += ok ? zj * zj : 0.f;
-            const float y = ok ? 2.f * sin2_pi(zj * tab[j]) : 0.f;
+            const float t = zj * zj;
+            const float yt = 2.f * sin2_pi(zj * tab[j]);
+            g1 += ok ? t : 0.f;
+            const float y = ok ? yt : 0.f;
             two_sum_into(a.s2, a.c2, y * (1.f - (a.s2 + a.c2)));
         } else {  // ACKLEY
-            g1 += ok ? zj * zj : 0.f;
-            g2 += ok ? sin2_pi(zj) : 0.f;
+            const float t = zj * zj;
+            const float st = sin2_pi(zj);
+            g1 += ok ? t : 0.f;
+            g2 += ok ? st : 0.f;
         }
     }
     two_sum_into(a.s1, a.c1, g1);

@@ -51,40 +51,66 @@ struct RunDev {
     int32_t out_index;
 };
 
-// Inclusive prefix minimum of (key, index) over the block, earlier index on
-// ties; returns this thread's prefix.
-__device__ __forceinline__ void prefix_min(float v, int idx, float *sPv, int *sPi, float &pv, int &pi)
+// (key, index) pairs are combined so that the earlier pair wins ties: over
+// positions in index order this gives the minimum key and, among equal
+// keys, the lowest index.
+__device__ __forceinline__ void keep_earlier(float &v, int &idx, float ov, int oi)
 {
-    const int tid = threadIdx.x;
+    if (ov <= v) { v = ov; idx = oi; }
+}
+
+// Inclusive prefix minimum of (key, index) over the block, earlier index on
+// ties; every thread's prefix is left in sPv / sPi (and returned).  Wave
+// scans by shuffles, then one exchange of the four wave totals.
+__device__ __forceinline__ void prefix_min(float v, int idx, float *sPv, int *sPi, float *sWv, int *sWi,
+                                           float &pv, int &pi)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const float ov = __shfl_up(v, off, 64);
+        const int oi = __shfl_up(idx, off, 64);
+        if (lane >= off) keep_earlier(v, idx, ov, oi);
+    }
+    if (lane == 63) { sWv[wave] = v; sWi[wave] = idx; }
+    __syncthreads();
+    if (wave > 0) {
+        float cv = sWv[0];
+        int ci = sWi[0];
+        for (int w = 1; w < wave; ++w) {
+            // carry (earlier waves) against wave w's total: the carry is earlier
+            float tv = sWv[w];
+            int ti = sWi[w];
+            keep_earlier(tv, ti, cv, ci);
+            cv = tv;
+            ci = ti;
+        }
+        keep_earlier(v, idx, cv, ci);
+    }
     sPv[tid] = v;
     sPi[tid] = idx;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        float ov = INFINITY;
-        int oi = 0;
-        if (tid >= off) { ov = sPv[tid - off]; oi = sPi[tid - off]; }
-        __syncthreads();
-        if (tid >= off && ov <= v) { v = ov; idx = oi; }
-        sPv[tid] = v;
-        sPi[tid] = idx;
-        __syncthreads();
-    }
     pv = v;
     pi = idx;
 }
 
-__device__ __forceinline__ double block_sum(double v, double *sRed)
+// Sums over the block of N doubles per thread (fixed order: lanes by a
+// shuffle tree, then waves 0..3 in order).  Every thread gets the sums.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double *sRed /* [4 * N] */)
 {
-    const int tid = threadIdx.x;
-    sRed[tid] = v;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) sRed[wave * N + k] = v[k];
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) sRed[tid] += sRed[tid + off];
-        __syncthreads();
-    }
-    const double r = sRed[0];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = ((sRed[k] + sRed[N + k]) + sRed[2 * N + k]) + sRed[3 * N + k];
     __syncthreads();
-    return r;
 }
 
 template <int KS>
@@ -150,8 +176,14 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
     __shared__ float sF[256], sCR[256];
     __shared__ float sPv[256];
     __shared__ int sPi[256];
-    __shared__ double sRed[256];
+    __shared__ float sWv[4];
+    __shared__ int sWi[4];
+    __shared__ double sRed[4 * 5];
     __shared__ double sZ[128];
+    // per-individual choices of the generation, read by the element loops
+    __shared__ int sDa[256], sDb[256], sDc[256], sJr[256], sFlag[256];
+    __shared__ float sFi[256];
+    __shared__ uint32_t sThr[256];
     __shared__ float sMF[16], sMCR[16];
     __shared__ int sPos, sG, sCopy;
     __shared__ float sBest, sBestB;
@@ -167,20 +199,25 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
     if (tid < 16) { sMF[tid] = 0.5f; sMCR[tid] = 0.5f; }
     if (tid == 0) { sPos = 0; sG = 0; sBest = INFINITY; sBestB = INFINITY; sCopy = -1; }
 
+    // Element loops: wave w takes coordinate blocks w, w + 4, ...; its lanes
+    // take individuals, so every access to the [D][npp] state is coalesced
+    // and the loads of one work item are independent of each other.
+    const int lane = tid & 63, wave = tid >> 6;
+
     // generation 0: x uniform in the box (double, then rounded to float)
-    if (tid < np) {
-        for (int jb = 0; jb * 4 < D; ++jb) {
-            const u32x4 w = draw(R.run_uid, seed32, 0, (uint32_t)tid, TAG_INIT_X, (uint32_t)jb);
+    for (int jb = wave; jb * 4 < D; jb += 4)
+        for (int i = lane; i < np; i += 64) {
+            const u32x4 w = draw(R.run_uid, seed32, 0, (uint32_t)i, TAG_INIT_X, (uint32_t)jb);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = jb * 4 + e;
-                if (j >= D) break;
-                const float x = (float)((double)R.lb + ((double)R.ub - (double)R.lb) * u24d(word(w, e)));
-                R.X[j * npp + tid] = x;
-                if (pso) { R.V[j * npp + tid] = 0.f; R.P[j * npp + tid] = x; }
+                if (j < D) {
+                    const float x = (float)((double)R.lb + ((double)R.ub - (double)R.lb) * u24d(word(w, e)));
+                    R.X[j * npp + i] = x;
+                    if (pso) { R.V[j * npp + i] = 0.f; R.P[j * npp + i] = x; }
+                }
             }
         }
-    }
     __syncthreads();
 
     int64_t fe = 0;
@@ -189,9 +226,8 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
     auto record = [&](const float *Y, const float *eY) {
         float pv;
         int pi;
-        prefix_min(tid < np ? err_key(eY[tid]) : INFINITY, tid, sPv, sPi, pv, pi);
         const float before = sBest;
-        __syncthreads();
+        prefix_min(tid < np ? err_key(eY[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
         if (tid < np && R.trace) {
             const int64_t c = fe + tid + 1;
             if (c % TRACE_EVERY == 0) {
@@ -211,27 +247,29 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
             for (int j = tid; j < D; j += 256) R.bestx[j] = Y[j * npp + cp];
         __syncthreads();
     };
+    // gbest = argmin e(p), lowest index on ties
+    auto global_best = [&]() {
+        float pv;
+        int pi;
+        prefix_min(tid < np ? err_key(R.eP[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
+        if (tid == 0) sG = sPi[255];
+        __syncthreads();
+    };
+    // dst[j][i] = src[j][i] for the individuals with sFlag[i] set
+    auto copy_flagged = [&](float *dst, const float *src) {
+        for (int j = wave; j < D; j += 4)
+            for (int i = lane; i < np; i += 64)
+                if (sFlag[i]) dst[j * npp + i] = src[j * npp + i];
+        __syncthreads();
+    };
 
     eval_pop<KS>(R, R.X, R.eX, sA, sO, sT, K);
     __syncthreads();
     record(R.X, R.eX);
     if (pso) {
-        float bv = INFINITY;
-        int bi = 0;
-        if (tid < np) { R.eP[tid] = R.eX[tid]; bv = err_key(R.eX[tid]); bi = tid; }
-        sPv[tid] = bv;
-        sPi[tid] = bi;
+        if (tid < np) R.eP[tid] = R.eX[tid];
         __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
-            if (tid < off) {
-                const float ov = sPv[tid + off];
-                const int oi = sPi[tid + off];
-                if (ov < sPv[tid] || (ov == sPv[tid] && oi < sPi[tid])) { sPv[tid] = ov; sPi[tid] = oi; }
-            }
-            __syncthreads();
-        }
-        if (tid == 0) sG = sPi[0];
-        __syncthreads();
+        global_best();
     }
     fe = np;
 
@@ -241,146 +279,143 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
         if (pso) {
             // ---- PSO: update, evaluate, personal and global bests ----
             const int g = sG;
-            if (tid < np) {
-                for (int jb = 0; jb * 2 < D; ++jb) {
-                    const u32x4 wd = draw(R.run_uid, seed32, t, (uint32_t)tid, TAG_PSO_R, (uint32_t)jb);
+            for (int jb = wave; jb * 2 < D; jb += 4)
+                for (int i = lane; i < np; i += 64) {
+                    const u32x4 wd = draw(R.run_uid, seed32, t, (uint32_t)i, TAG_PSO_R, (uint32_t)jb);
+                    float xj[2], vv[2], pj[2], pg[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int row = min(jb * 2 + e, D - 1) * npp;
+                        xj[e] = R.X[row + i];
+                        vv[e] = R.V[row + i];
+                        pj[e] = R.P[row + i];
+                        pg[e] = R.P[row + g];
+                    }
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const int j = jb * 2 + e;
-                        if (j >= D) break;
-                        const int row = j * npp;
-                        const float r1 = u24f(word(wd, 2 * e)), r2 = u24f(word(wd, 2 * e + 1));
-                        const float xj = R.X[row + tid];
-                        float vj = R.w * R.V[row + tid] + R.c1 * r1 * (R.P[row + tid] - xj) +
-                                   R.c2 * r2 * (R.P[row + g] - xj);
-                        vj = fminf(fmaxf(vj, -R.vmax), R.vmax);
-                        float xn = xj + vj;
-                        if (xn < R.lb) { xn = R.lb; vj = 0.f; }
-                        else if (xn > R.ub) { xn = R.ub; vj = 0.f; }
-                        R.X[row + tid] = xn;
-                        R.V[row + tid] = vj;
+                        if (j < D) {
+                            const int row = j * npp;
+                            const float r1 = u24f(word(wd, 2 * e)), r2 = u24f(word(wd, 2 * e + 1));
+                            float vj = R.w * vv[e] + R.c1 * r1 * (pj[e] - xj[e]) + R.c2 * r2 * (pg[e] - xj[e]);
+                            vj = fminf(fmaxf(vj, -R.vmax), R.vmax);
+                            float xn = xj[e] + vj;
+                            if (xn < R.lb) { xn = R.lb; vj = 0.f; }
+                            else if (xn > R.ub) { xn = R.ub; vj = 0.f; }
+                            R.X[row + i] = xn;
+                            R.V[row + i] = vj;
+                        }
                     }
                 }
-            }
             __syncthreads();
             eval_pop<KS>(R, R.X, R.eX, sA, sO, sT, K);
             __syncthreads();
             record(R.X, R.eX);
-            float bv = INFINITY;
-            int bi = 0;
             if (tid < np) {
-                if (err_key(R.eX[tid]) < err_key(R.eP[tid])) {
-                    R.eP[tid] = R.eX[tid];
-                    for (int j = 0; j < D; ++j) R.P[j * npp + tid] = R.X[j * npp + tid];
-                }
-                bv = err_key(R.eP[tid]);
-                bi = tid;
+                const bool imp = err_key(R.eX[tid]) < err_key(R.eP[tid]);
+                if (imp) R.eP[tid] = R.eX[tid];
+                sFlag[tid] = imp ? 1 : 0;
             }
-            sPv[tid] = bv;
-            sPi[tid] = bi;
             __syncthreads();
-            for (int off = 128; off > 0; off >>= 1) {
-                if (tid < off) {
-                    const float ov = sPv[tid + off];
-                    const int oi = sPi[tid + off];
-                    if (ov < sPv[tid] || (ov == sPv[tid] && oi < sPi[tid])) { sPv[tid] = ov; sPi[tid] = oi; }
-                }
-                __syncthreads();
-            }
-            if (tid == 0) sG = sPi[0];
-            __syncthreads();
+            copy_flagged(R.P, R.X);
+            global_best();
         } else {
             // ---- DE rand/1/bin or SHADE current-to-pbest/1 ----
             if (shade) {
-                // ranking by (error, index): bitonic sort of 256 keys
-                unsigned long long key = ~0ull;
+                // ranking by (error, index): every key counts the keys below it
                 if (tid < np) {
                     const uint32_t bits = __float_as_uint(err_key(R.eX[tid]));
                     const uint32_t ord = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
-                    key = ((unsigned long long)ord << 32) | (uint32_t)tid;
+                    sKey[tid] = ((unsigned long long)ord << 32) | (uint32_t)tid;
                 }
-                sKey[tid] = key;
                 __syncthreads();
-                for (int k = 2; k <= 256; k <<= 1) {
-                    for (int j = k >> 1; j > 0; j >>= 1) {
-                        const int ixj = tid ^ j;
-                        if (ixj > tid) {
-                            const unsigned long long a = sKey[tid], b = sKey[ixj];
-                            const bool asc = (tid & k) == 0;
-                            if ((a > b) == asc) { sKey[tid] = b; sKey[ixj] = a; }
-                        }
-                        __syncthreads();
-                    }
+                if (tid < np) {
+                    const unsigned long long key = sKey[tid];
+                    int rank = 0;
+                    for (int q = 0; q < np; ++q) rank += sKey[q] < key ? 1 : 0;
+                    sRank[rank] = tid;
                 }
-                sRank[tid] = (int)(uint32_t)sKey[tid];
                 __syncthreads();
             }
             if (tid < np) {
                 const int i = tid;
-                float Fi = R.F;
-                uint32_t thr = R.thr;
-                int ia, ib, ic, jrand, pb = 0;
                 if (shade) {
                     const ShadeDraw d = shade_draw(R.run_uid, seed32, t, i, np, D, R.H, R.pnum, sMF, sMCR);
-                    Fi = d.F;
-                    thr = cr_threshold((double)d.CR);
                     sF[i] = d.F;
                     sCR[i] = d.CR;
-                    pb = sRank[d.pbest_rank];
-                    ia = d.r1;
-                    ib = d.r2;
-                    ic = 0;
-                    jrand = d.jrand;
+                    sFi[i] = d.F;
+                    sThr[i] = cr_threshold((double)d.CR);
+                    sDa[i] = d.r1;
+                    sDb[i] = d.r2;
+                    sDc[i] = sRank[d.pbest_rank];
+                    sJr[i] = d.jrand;
                 } else {
+                    int ia, ib, ic, jrand;
                     de_donors(R.run_uid, seed32, t, i, np, D, ia, ib, ic, jrand);
+                    sFi[i] = R.F;
+                    sThr[i] = R.thr;
+                    sDa[i] = ia;
+                    sDb[i] = ib;
+                    sDc[i] = ic;
+                    sJr[i] = jrand;
                 }
-                for (int jb = 0; jb * 4 < D; ++jb) {
+            }
+            __syncthreads();
+            for (int jb = wave; jb * 4 < D; jb += 4)
+                for (int i = lane; i < np; i += 64) {
                     const u32x4 w = draw(R.run_uid, seed32, t, (uint32_t)i, TAG_CROSS, (uint32_t)jb);
+                    const int ia = sDa[i], ib = sDb[i], ic = sDc[i], jrand = sJr[i];
+                    const float Fi = sFi[i];
+                    const uint32_t thr = sThr[i];
+                    float xi[4], xa[4], xb[4], xc[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = min(jb * 4 + e, D - 1) * npp;
+                        xi[e] = R.X[row + i];
+                        xa[e] = R.X[row + ia];
+                        xb[e] = R.X[row + ib];
+                        xc[e] = R.X[row + ic];
+                    }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int j = jb * 4 + e;
-                        if (j >= D) break;
-                        const int row = j * npp;
-                        const float xi = R.X[row + i];
-                        float v;
-                        if (shade) v = xi + Fi * (R.X[row + pb] - xi) + Fi * (R.X[row + ia] - R.X[row + ib]);
-                        else v = R.X[row + ia] + Fi * (R.X[row + ib] - R.X[row + ic]);
-                        bool m;
-                        R.U[row + i] = cross_repair<float>(word(w, e), thr, j, jrand, v, xi, R.lb, R.ub, m);
+                        if (j < D) {
+                            // SHADE: ic is the pbest individual, v = x + F (x_pbest - x) + F (x_r1 - x_r2)
+                            float v;
+                            if (shade) v = xi[e] + Fi * (xc[e] - xi[e]) + Fi * (xa[e] - xb[e]);
+                            else v = xa[e] + Fi * (xb[e] - xc[e]);
+                            bool m;
+                            R.U[j * npp + i] = cross_repair<float>(word(w, e), thr, j, jrand, v, xi[e], R.lb, R.ub, m);
+                        }
                     }
                 }
-            }
             __syncthreads();
             eval_pop<KS>(R, R.U, R.eU, sA, sO, sT, K);
             __syncthreads();
             record(R.U, R.eU);
-            double dsum = 0.0, dcr = 0.0, df2 = 0.0, df = 0.0, nsucc = 0.0;
+            double st[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum dl, dl CR, dl F^2, dl F, successes
             if (tid < np) {
                 const float ku = err_key(R.eU[tid]), kx = err_key(R.eX[tid]);
                 if (shade && ku < kx) {
                     double dl = (double)kx - (double)ku;
                     if (!(dl <= 1e30)) dl = 1e30;
-                    dsum = dl;
-                    dcr = dl * sCR[tid];
-                    df2 = dl * sF[tid] * sF[tid];
-                    df = dl * sF[tid];
-                    nsucc = 1.0;
+                    st[0] = dl;
+                    st[1] = dl * sCR[tid];
+                    st[2] = dl * sF[tid] * sF[tid];
+                    st[3] = dl * sF[tid];
+                    st[4] = 1.0;
                 }
-                if (ku <= kx) {
-                    R.eX[tid] = R.eU[tid];
-                    for (int j = 0; j < D; ++j) R.X[j * npp + tid] = R.U[j * npp + tid];
-                }
+                const bool rep = ku <= kx;
+                if (rep) R.eX[tid] = R.eU[tid];
+                sFlag[tid] = rep ? 1 : 0;
             }
             __syncthreads();
+            copy_flagged(R.X, R.U);
             if (shade) {
-                const double S0 = block_sum(dsum, sRed);
-                const double S1 = block_sum(dcr, sRed);
-                const double S2 = block_sum(df2, sRed);
-                const double S3 = block_sum(df, sRed);
-                const double NS = block_sum(nsucc, sRed);
-                if (tid == 0 && NS > 0.0) {
-                    sMCR[sPos] = (float)(S1 / S0);
-                    sMF[sPos] = (float)(S2 / S3);
+                block_sums<5>(st, sRed);
+                if (tid == 0 && st[4] > 0.0) {
+                    sMCR[sPos] = (float)(st[1] / st[0]);
+                    sMF[sPos] = (float)(st[2] / st[3]);
                     sPos = (sPos + 1) % R.H;
                 }
                 __syncthreads();

@@ -29,6 +29,8 @@ __device__ __forceinline__ SEVO_GLOBAL T *gout(void *p)
 // 16-row tiles by 4-column steps) lives in LDS, <= 62 KB.
 constexpr int SMALL_D_MAX = 120;
 constexpr int MAX_DIM = 1024;
+// Largest leading dimension of a population (32-bit per-lane load offsets).
+constexpr int64_t MAX_LD = int64_t(1) << 28;
 
 // One evaluation item as the kernels see it (a population of one
 // (function, dimension, instance)).

@@ -726,6 +726,7 @@ int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_it
         if (it.n < 0) return fail(ctx, SEVO_EINVAL, "item %d: n = %d", i, it.n);
         if (it.n == 0) continue;
         if (it.ld < it.n) return fail(ctx, SEVO_EINVAL, "item %d: ld %lld < n %d", i, (long long)it.ld, it.n);
+        if (it.ld > MAX_LD) return fail(ctx, SEVO_EINVAL, "item %d: ld %lld > 2^28", i, (long long)it.ld);
         if (!it.x || !it.err_out) return fail(ctx, SEVO_EINVAL, "item %d: null buffer", i);
         DevInstance *I = nullptr;
         if ((rc = get_instance(ctx, &it.prob, it.instance, &I))) return rc;

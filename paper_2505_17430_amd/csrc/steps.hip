@@ -275,6 +275,7 @@ int check_common(sevo_ctx *ctx, const sevo_problem *prob, int n_runs, int np, in
     if (n_runs < 1) return set_error(ctx, SEVO_EINVAL, "n_runs < 1");
     if (np < min_np) return set_error(ctx, SEVO_EINVAL, "population too small");
     if (ld < np) return set_error(ctx, SEVO_EINVAL, "ld < np");
+    if (ld > MAX_LD) return set_error(ctx, SEVO_EINVAL, "ld > 2^28");
     if (rs < (int64_t)prob->dim * ld) return set_error(ctx, SEVO_EINVAL, "run_stride < dim * ld");
     return SEVO_OK;
 }

@@ -15,76 +15,89 @@ namespace sevo {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Rotation and objective of one wave's 16*CT points: for every 16-row tile
-// of z the K loop runs on MFMA (A from LDS, B = the shifted points held in
-// registers), then the tile's rows are folded into per-lane compensated
-// accumulators straight from the accumulator registers.  Rosenbrock needs
-// z_{r+1}: row 4q+3 of lane group q takes row 4q+4 from lane l+16, and the
-// last row of a tile takes row 0 of the next tile (lane l-48), so its terms
-// are added one tile late.
+// z rows 16 rt .. 16 rt + 15 of the wave's 16*CT points: the K loop on
+// MFMA with A (the rotation fragments) from LDS and B (the shifted points)
+// from registers.  With one column tile the even and odd k-steps go to two
+// accumulators, so that two independent MFMA chains are in flight.
+template <int KS, int CT>
+__device__ __forceinline__ void rotate_rows(floatx4 (&z)[CT], const float (&b)[KS][CT], const float *sA,
+                                            int rt, int lane)
+{
+    if constexpr (CT == 1) {
+        floatx4 z0 = floatx4{0.f, 0.f, 0.f, 0.f}, z1 = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const float a = sA[(rt * KS + ks) * 64 + lane];
+            if (ks & 1) z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks][0], z1, 0, 0, 0);
+            else z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks][0], z0, 0, 0, 0);
+        }
+        z[0] = z0 + z1;
+    } else {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) z[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const float a = sA[(rt * KS + ks) * 64 + lane];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) z[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks][c], z[c], 0, 0, 0);
+        }
+    }
+}
+
+// Fold row tile rt (zc) into the per-lane accumulators; zn is row tile
+// rt + 1 (zeros after the last), which Rosenbrock's z_{r+1} needs for the
+// last row of a lane group: row 4q+3 of lane group q takes row 4q+4 from
+// lane l+16, and group 3 takes row 0 of the next tile (lane l-48).
+template <int FUNC, int CT>
+__device__ __forceinline__ void fold_rows(AccF (&acc)[CT], const floatx4 (&zc)[CT], const floatx4 (&zn)[CT],
+                                          const float *sT, int rt, int lane, int dim,
+                                          const SchwefelConst<float> &K)
+{
+    const int kq = lane >> 4;
+    const int r0 = rt * 16 + kq * 4;
+    const int valid = min(max(dim - r0, 0), 4);
+    const float t4[4] = {sT[r0], sT[r0 + 1], sT[r0 + 2], sT[r0 + 3]};
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const float z4[4] = {zc[c][0], zc[c][1], zc[c][2], zc[c][3]};
+        float nx3 = 0.f;
+        if constexpr (FUNC == ROSENBROCK) {
+            const int src = (lane + 16) & 63;
+            const float same = __shfl(zc[c][0], src, 64);
+            const float next = __shfl(zn[c][0], src, 64);
+            nx3 = kq < 3 ? same : next;
+        }
+        add_group<FUNC>(acc[c], z4, nx3, valid, r0 + 4 < dim, t4, K);
+    }
+}
+
+// Rotation and objective of one wave's 16*CT points.  The row tiles are
+// software-pipelined: the MFMA chain of tile rt + 1 is issued before the
+// objective of tile rt is folded, so matrix-core and vector work of one wave
+// overlap, and z never leaves the registers.
 template <int FUNC, int KS, int CT>
 __device__ __forceinline__ void tile_body(const float (&b)[KS][CT], const float *sA, const float *sT,
                                           int lane, int dim, int n, int p0,
                                           const SchwefelConst<float> &K, SEVO_GLOBAL float *__restrict__ E)
 {
     constexpr int RT = (KS + 3) / 4;
-    const int kq = lane >> 4;
-    const int src = (lane + 16) & 63;
     AccF acc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[c].init();
-    floatx4 zp[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) zp[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-
+    floatx4 zc[CT], zn[CT];
+    rotate_rows<KS, CT>(zc, b, sA, 0, lane);
 #pragma nounroll
-    for (int rt = 0; rt < RT; ++rt) {
-        floatx4 zc[CT];
+    for (int rt = 0; rt < RT - 1; ++rt) {
+        rotate_rows<KS, CT>(zn, b, sA, rt + 1, lane);
+        fold_rows<FUNC, CT>(acc, zc, zn, sT, rt, lane, dim, K);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) zc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float a = sA[(rt * KS + ks) * 64 + lane];
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                zc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ks][c], zc[c], 0, 0, 0);
-        }
-        if constexpr (FUNC == ROSENBROCK) {
-            if (rt > 0) {
-                const int r0 = (rt - 1) * 16 + kq * 4;
-                const int valid = min(max(dim - r0, 0), 4);
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    const float nx_same = __shfl(zp[c][0], src, 64);
-                    const float nx_next = __shfl(zc[c][0], src, 64);
-                    const float z4[4] = {zp[c][0], zp[c][1], zp[c][2], zp[c][3]};
-                    add_group<FUNC>(acc[c], z4, kq < 3 ? nx_same : nx_next, valid, r0 + 4 < dim, sT + r0, K);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < CT; ++c) zp[c] = zc[c];
-        } else {
-            const int r0 = rt * 16 + kq * 4;
-            const int valid = min(max(dim - r0, 0), 4);
-            const float t4[4] = {sT[r0], sT[r0 + 1], sT[r0 + 2], sT[r0 + 3]};
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const float z4[4] = {zc[c][0], zc[c][1], zc[c][2], zc[c][3]};
-                add_group<FUNC>(acc[c], z4, 0.f, valid, false, t4, K);
-            }
-        }
+        for (int c = 0; c < CT; ++c) zc[c] = zn[c];
     }
-    if constexpr (FUNC == ROSENBROCK) {
-        const int r0 = (RT - 1) * 16 + kq * 4;
-        const int valid = min(max(dim - r0, 0), 4);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            const float nb3 = __shfl(zp[c][0], src, 64);
-            const float z4[4] = {zp[c][0], zp[c][1], zp[c][2], zp[c][3]};
-            add_group<FUNC>(acc[c], z4, kq < 3 ? nb3 : 0.f, valid, kq < 3 && r0 + 4 < dim, sT + r0, K);
-        }
-    }
-    const int pc = lane & 15;
+    for (int c = 0; c < CT; ++c) zn[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    fold_rows<FUNC, CT>(acc, zc, zn, sT, RT - 1, lane, dim, K);
+
+    const int kq = lane >> 4, pc = lane & 15;
     const float inv_dim = 1.f / (float)dim;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
@@ -95,23 +108,38 @@ __device__ __forceinline__ void tile_body(const float (&b)[KS][CT], const float 
     }
 }
 
-// Coordinates of one wave's 16*CT points, in two halves so a caller can
-// keep the loads of the next tile in flight while it computes the current
-// one: load_raw only issues the loads (unconditional, from a clamped and
-// therefore always valid address -- a load under a per-lane branch would be
-// waited for before the next one is issued); shift_raw then masks the
-// padding and applies the shift in double, rounding d = x - o once to float.
+// Coordinates of one wave's 16*CT points (p0 is the same for the whole
+// wave), in two halves so a caller can keep the loads of the next tile in
+// flight while it computes the current one.  load_raw only issues the
+// loads: unconditional, from clamped and therefore always valid addresses
+// (a load under a per-lane branch would be waited for before the next one
+// is issued), each a wave-uniform row base plus a 32-bit per-lane byte
+// offset (rows 4 ks .. 4 ks + 3 of lane group kq; points past n re-read
+// point n - 1; rows past dim, which only the last k-step has, re-read row
+// dim - 1).  Offsets stay below 2^32 for ld < 2^28, which the entry points
+// check.  shift_raw then applies the shift in double, rounding d = x - o
+// once to float, and zeroes rows past dim.
 template <int KS, int CT>
 __device__ __forceinline__ void load_raw(float (&raw)[KS][CT], const SEVO_GLOBAL float *__restrict__ X,
                                          int64_t ld, int dim, int n, int p0, int kq, int pc)
 {
+    const int pb = __builtin_amdgcn_readfirstlane(min(p0, n - 1));
+    const SEVO_GLOBAL char *base = reinterpret_cast<const SEVO_GLOBAL char *>(X + pb);
+    const int last = min(kq, dim - 1 - 4 * (KS - 1));
+    uint32_t off[CT], offl[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const uint32_t pl = (uint32_t)(min(p0 + c * 16 + pc, n - 1) - pb);
+        off[c] = ((uint32_t)kq * (uint32_t)ld + pl) * 4u;
+        offl[c] = ((uint32_t)last * (uint32_t)ld + pl) * 4u;
+    }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const int k = min(ks * 4 + kq, dim - 1);
+        const SEVO_GLOBAL char *row = base + (int64_t)(4 * ks) * ld * 4;
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            const int p = min(p0 + c * 16 + pc, n - 1);
-            raw[ks][c] = X[(int64_t)k * ld + p];
+            const uint32_t o = ks == KS - 1 ? offl[c] : off[c];
+            raw[ks][c] = *reinterpret_cast<const SEVO_GLOBAL float *>(row + o);
         }
     }
 }
@@ -120,14 +148,15 @@ template <int KS, int CT>
 __device__ __forceinline__ void shift_raw(float (&b)[KS][CT], int dim, int n, int p0, int kq, int pc,
                                           const double *sO)
 {
+    (void)n; (void)p0; (void)pc;   // lanes past n compute on a copy of point n - 1 and store nothing
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k = ks * 4 + kq;
         const double ok = sO[k];
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            const int p = p0 + c * 16 + pc;
-            b[ks][c] = (k < dim && p < n) ? (float)((double)b[ks][c] - ok) : 0.f;
+            const float d = (float)((double)b[ks][c] - ok);
+            b[ks][c] = (ks < KS - 1 || k < dim) ? d : 0.f;
         }
     }
 }
