@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -42,13 +43,45 @@ struct RunDev {
     const float *Mfrag;
     const float *tab;
     const double *M64;
-    float *X, *U, *V, *P, *eX, *eU, *eP, *bestx;
+    float *X, *U, *V, *P, *bestx;   // workspace (X .. P unused when on chip)
     sevo_run_result *res;
     float *trace;
     int64_t trace_len;
     double *best_x_out;
     int32_t max_dim;
     int32_t out_index;
+};
+
+// A team carries one run: the whole workgroup (256 threads, phases separated
+// by block barriers) or one wave (64 lanes, which run in lockstep: phases
+// only need the team's memory operations ordered, no barrier).  The four
+// wave teams of a workgroup run four runs of the same instance, which is
+// staged in LDS once for all of them.
+template <bool WAVE>
+struct Team;
+
+template <>
+struct Team<false> {
+    static constexpr int SIZE = 256, NW = 4;
+    int tid, lane, wave, slot;
+    __device__ Team() : tid(threadIdx.x), lane(threadIdx.x & 63), wave(threadIdx.x >> 6), slot(0) {}
+    __device__ static void sync() { __syncthreads(); }
+};
+
+template <>
+struct Team<true> {
+    static constexpr int SIZE = 64, NW = 1;
+    int tid, lane, wave, slot;
+    // slot is wave-uniform; saying so keeps the run's descriptor in scalar registers
+    __device__ Team()
+        : tid(threadIdx.x & 63), lane(threadIdx.x & 63), wave(0),
+          slot(__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) {}
+    __device__ static void sync()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
 };
 
 // (key, index) pairs are combined so that the earlier pair wins ties: over
@@ -59,98 +92,123 @@ __device__ __forceinline__ void keep_earlier(float &v, int &idx, float ov, int o
     if (ov <= v) { v = ov; idx = oi; }
 }
 
-// Inclusive prefix minimum of (key, index) over the block, earlier index on
-// ties; every thread's prefix is left in sPv / sPi (and returned).  Wave
-// scans by shuffles, then one exchange of the four wave totals.
-__device__ __forceinline__ void prefix_min(float v, int idx, float *sPv, int *sPi, float *sWv, int *sWi,
-                                           float &pv, int &pi)
+// Inclusive prefix minimum of (key, index) over the team, earlier index on
+// ties; every member's prefix is left in sPv / sPi (the team's slices) and
+// returned.  Wave scans by shuffles; a block team then exchanges the four
+// wave totals.
+template <bool WAVE>
+__device__ __forceinline__ void prefix_min(const Team<WAVE> &t, float v, int idx, float *sPv, int *sPi,
+                                           float *sWv, int *sWi, float &pv, int &pi)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const float ov = __shfl_up(v, off, 64);
         const int oi = __shfl_up(idx, off, 64);
-        if (lane >= off) keep_earlier(v, idx, ov, oi);
+        if (t.lane >= off) keep_earlier(v, idx, ov, oi);
     }
-    if (lane == 63) { sWv[wave] = v; sWi[wave] = idx; }
-    __syncthreads();
-    if (wave > 0) {
-        float cv = sWv[0];
-        int ci = sWi[0];
-        for (int w = 1; w < wave; ++w) {
-            // carry (earlier waves) against wave w's total: the carry is earlier
-            float tv = sWv[w];
-            int ti = sWi[w];
-            keep_earlier(tv, ti, cv, ci);
-            cv = tv;
-            ci = ti;
+    if constexpr (!WAVE) {
+        if (t.lane == 63) { sWv[t.wave] = v; sWi[t.wave] = idx; }
+        __syncthreads();
+        if (t.wave > 0) {
+            float cv = sWv[0];
+            int ci = sWi[0];
+            for (int w = 1; w < t.wave; ++w) {
+                // carry (earlier waves) against wave w's total: the carry is earlier
+                float tv = sWv[w];
+                int ti = sWi[w];
+                keep_earlier(tv, ti, cv, ci);
+                cv = tv;
+                ci = ti;
+            }
+            keep_earlier(v, idx, cv, ci);
         }
-        keep_earlier(v, idx, cv, ci);
     }
-    sPv[tid] = v;
-    sPi[tid] = idx;
-    __syncthreads();
+    sPv[t.tid] = v;
+    sPi[t.tid] = idx;
+    t.sync();
     pv = v;
     pi = idx;
 }
 
-// Sums over the block of N doubles per thread (fixed order: lanes by a
-// shuffle tree, then waves 0..3 in order).  Every thread gets the sums.
-template <int N>
-__device__ __forceinline__ void block_sums(double (&v)[N], double *sRed /* [4 * N] */)
+// Sums over the team of N doubles per member, in a fixed order (lanes by a
+// shuffle tree, then waves 0..3 in order); every member gets the sums.
+template <int N, bool WAVE>
+__device__ __forceinline__ void team_sums(const Team<WAVE> &t, double (&v)[N], double *sRed /* [4 * N] */)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    if (lane == 0)
+    if constexpr (!WAVE) {
+        if (t.lane == 0)
 #pragma unroll
-        for (int k = 0; k < N; ++k) sRed[wave * N + k] = v[k];
-    __syncthreads();
+            for (int k = 0; k < N; ++k) sRed[t.wave * N + k] = v[k];
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = ((sRed[k] + sRed[N + k]) + sRed[2 * N + k]) + sRed[3 * N + k];
-    __syncthreads();
+        for (int k = 0; k < N; ++k) v[k] = ((sRed[k] + sRed[N + k]) + sRed[2 * N + k]) + sRed[3 * N + k];
+        __syncthreads();
+    }
 }
 
-template <int KS>
-__device__ __forceinline__ void eval_pop(const RunDev &R, const float *Y, float *eY, const float *sA,
-                                         const double *sO, const float *sT, const Consts &K)
+// Errors of the np points Y ([dim][npp], in LDS when ONCHIP, else in the
+// workspace) into eY (LDS): the team's waves take 16-point tiles in turn.
+template <int KS, bool ONCHIP, bool WAVE>
+__device__ __forceinline__ void eval_pop(const Team<WAVE> &t, const RunDev &R, const float *Y, float *eY,
+                                         const float *sA, const double *sO, const float *sT, const Consts &K)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = t.lane;
     const int kq = lane >> 4, pc = lane & 15;
     const int ntile = (R.np + 15) / 16;
-    for (int ct = wave; ct < ntile; ct += 4) {
-        const int p0 = ct * 16;
-        float b[KS][1];
-        load_b<KS, 1>(b, gin<float>(Y), R.npp, R.dim, R.np, p0, kq, pc, sO);
-        SEVO_GLOBAL float *E = gout<float>(eY);
+    constexpr int NW = Team<WAVE>::NW;
+    // from the workspace, the next tile's loads are in flight while the
+    // current one is computed (while the extra registers are affordable)
+    constexpr bool PF = !ONCHIP && KS <= 13;
+    auto load = [&](float (&dst)[KS][1], int p0) {
+        if constexpr (ONCHIP) load_raw_lds<KS, 1>(dst, Y, R.npp, R.dim, R.np, p0, kq, pc);
+        else load_raw<KS, 1>(dst, gin<float>(Y), R.npp, R.dim, R.np, p0, kq, pc);
+    };
+    float b[KS][1], bn[KS][1];
+    if (t.wave < ntile) load(b, t.wave * 16);
+    for (int ct = t.wave; ct < ntile; ct += NW) {
+        const int p0 = ct * 16, nx = ct + NW;
+        if constexpr (PF)
+            if (nx < ntile) load(bn, nx * 16);
+        shift_raw<KS, 1>(b, R.dim, R.np, p0, kq, pc, sO);
         switch (R.func) {
-        case ELLIPSOID: tile_body<ELLIPSOID, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, E); break;
-        case ROSENBROCK: tile_body<ROSENBROCK, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, E); break;
-        case RASTRIGIN: tile_body<RASTRIGIN, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, E); break;
-        case SCHWEFEL: tile_body<SCHWEFEL, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, E); break;
-        case GRIEWANK: tile_body<GRIEWANK, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, E); break;
-        default: tile_body<ACKLEY, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, E); break;
+        case ELLIPSOID: tile_body<ELLIPSOID, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        case ROSENBROCK: tile_body<ROSENBROCK, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        case RASTRIGIN: tile_body<RASTRIGIN, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        case SCHWEFEL: tile_body<SCHWEFEL, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        case GRIEWANK: tile_body<GRIEWANK, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        default: tile_body<ACKLEY, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        }
+        if (nx < ntile) {
+            if constexpr (PF) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k) b[k][0] = bn[k][0];
+            } else {
+                load(b, nx * 16);
+            }
         }
     }
 }
 
 // Double-precision error of one float point (the final check): rows of z by
-// all threads into LDS, then the objective by thread 0.  Every thread of the
-// workgroup must call it.
-template <int FUNC>
-__device__ __forceinline__ double check_f64(const RunDev &R, const float *x, double *sZ, const Consts &K)
+// the team into sZ, then the objective by the team's first member (the
+// value is valid there only).  Every member of the team must call it.
+template <int FUNC, bool WAVE>
+__device__ __forceinline__ double check_f64(const Team<WAVE> &t, const RunDev &R, const float *x, double *sZ,
+                                            const Consts &K)
 {
     const int D = R.dim;
-    for (int r = threadIdx.x; r < D; r += 256) {
+    for (int r = t.tid; r < D; r += Team<WAVE>::SIZE) {
         double z = 0.0;
         for (int k = 0; k < D; ++k) z = fma(R.M64[(int64_t)r * D + k], (double)x[k] - R.o[k], z);
         sZ[r] = z;
     }
-    __syncthreads();
+    t.sync();
     double e = 0.0;
-    if (threadIdx.x == 0) {
+    if (t.tid == 0) {
         Acc<double> acc;
         acc.init();
         for (int r = 0; r < D; ++r) {
@@ -164,48 +222,89 @@ __device__ __forceinline__ double check_f64(const RunDev &R, const float *x, dou
     return e;
 }
 
-template <int KS>
-__global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, uint32_t seed32, Consts K)
+// Whole runs.  WAVE: four runs per workgroup, one per wave, all of the same
+// instance (the host groups them; a slot with np = 0 is empty); otherwise
+// one run per workgroup.  ONCHIP: each run's population (X and U, or X, V
+// and P for PSO) lives in dynamic LDS, dyn_stride floats per run; otherwise
+// in the library workspace.
+template <int KS, bool ONCHIP, bool WAVE>
+__global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs, uint32_t seed32, Consts K,
+                                                int dyn_stride)
 {
+    extern __shared__ __attribute__((aligned(16))) float sDyn[];
     constexpr int RT = (KS + 3) / 4;
+    constexpr int TS = Team<WAVE>::SIZE;
     __shared__ __attribute__((aligned(16))) float sA[RT * KS * 64];
     __shared__ double sO[KS * 4];
     __shared__ float sT[RT * 16];
-    __shared__ unsigned long long sKey[256];
-    __shared__ int sRank[256];
-    __shared__ float sF[256], sCR[256];
-    __shared__ float sPv[256];
-    __shared__ int sPi[256];
+    // per-individual arrays: 256 entries, one 64-entry slice per wave team
+    __shared__ unsigned long long sKeyA[256];
+    __shared__ int sRankA[256];
+    __shared__ float sFA[256], sCRA[256];
+    __shared__ float sPvA[256];
+    __shared__ int sPiA[256];
+    __shared__ int sDaA[256], sDbA[256], sDcA[256], sJrA[256], sFlagA[256];
+    __shared__ float sFiA[256];
+    __shared__ uint32_t sThrA[256];
+    __shared__ float sEXA[256], sEUA[256], sEPA[256];   // errors of x, of trials / new positions, of pbests
     __shared__ float sWv[4];
     __shared__ int sWi[4];
     __shared__ double sRed[4 * 5];
-    __shared__ double sZ[128];
-    // per-individual choices of the generation, read by the element loops
-    __shared__ int sDa[256], sDb[256], sDc[256], sJr[256], sFlag[256];
-    __shared__ float sFi[256];
-    __shared__ uint32_t sThr[256];
-    __shared__ float sMF[16], sMCR[16];
-    __shared__ int sPos, sG, sCopy;
-    __shared__ float sBest, sBestB;
+    __shared__ double sZA[WAVE ? 4 : 1][128];
+    // per-team scalars
+    __shared__ float sMFA[4][16], sMCRA[4][16];
+    __shared__ int sPosA[4], sGA[4], sCopyA[4];
+    __shared__ float sBestA[4], sBestBA[4];
 
-    const RunDev R = runs[blockIdx.x];
-    const int tid = threadIdx.x;
+    const Team<WAVE> t;
+    const int tid = t.tid, s = t.slot, base = WAVE ? s * 64 : 0;
+    const int run_index = WAVE ? blockIdx.x * 4 + s : blockIdx.x;
+
+    // the instance, shared by the workgroup's runs
+    {
+        const RunDev &R0 = runs[WAVE ? blockIdx.x * 4 : blockIdx.x];
+        stage_rotation<KS>(sA, R0.Mfrag);
+        const int D0 = R0.dim;
+        for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < D0 ? R0.o[q] : 0.0;
+        for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = R0.tab[q];
+    }
+    __syncthreads();
+
+    const RunDev R = runs[run_index];
+    if (WAVE && R.np == 0) return;   // empty slot: no barrier follows for wave teams
     const int D = R.dim, np = R.np, npp = R.npp;
     const bool pso = R.algo == SEVO_ALGO_PSO, shade = R.algo == SEVO_ALGO_SHADE;
-
-    stage_rotation<KS>(sA, R.Mfrag);
-    for (int q = tid; q < KS * 4; q += 256) sO[q] = q < D ? R.o[q] : 0.0;
-    for (int q = tid; q < RT * 16; q += 256) sT[q] = R.tab[q];
+    float *X, *U, *V, *P;
+    if constexpr (ONCHIP) {
+        X = sDyn + (WAVE ? s * dyn_stride : 0);
+        U = X + D * npp;   // PSO keeps its velocities here
+        V = U;
+        P = X + 2 * D * npp;
+    } else {
+        X = R.X;
+        U = R.U;
+        V = R.V;
+        P = R.P;
+    }
+    unsigned long long *sKey = sKeyA + base;
+    int *sRank = sRankA + base, *sPi = sPiA + base;
+    int *sDa = sDaA + base, *sDb = sDbA + base, *sDc = sDcA + base, *sJr = sJrA + base, *sFlag = sFlagA + base;
+    float *sF = sFA + base, *sCR = sCRA + base, *sPv = sPvA + base, *sFi = sFiA + base;
+    uint32_t *sThr = sThrA + base;
+    float *sEX = sEXA + base, *sEU = sEUA + base, *sEP = sEPA + base;
+    float *sMF = sMFA[s], *sMCR = sMCRA[s];
+    double *sZ = sZA[WAVE ? s : 0];
     if (tid < 16) { sMF[tid] = 0.5f; sMCR[tid] = 0.5f; }
-    if (tid == 0) { sPos = 0; sG = 0; sBest = INFINITY; sBestB = INFINITY; sCopy = -1; }
+    if (tid == 0) { sPosA[s] = 0; sGA[s] = 0; sBestA[s] = INFINITY; sBestBA[s] = INFINITY; sCopyA[s] = -1; }
 
-    // Element loops: wave w takes coordinate blocks w, w + 4, ...; its lanes
-    // take individuals, so every access to the [D][npp] state is coalesced
-    // and the loads of one work item are independent of each other.
-    const int lane = tid & 63, wave = tid >> 6;
+    // Element loops: the team's wave w takes coordinate blocks w, w + NW, ...;
+    // its lanes take individuals, so every access to the [D][npp] state is
+    // coalesced and the loads of one work item are independent of each other.
+    const int lane = t.lane, wave = t.wave;
+    constexpr int NW = Team<WAVE>::NW;
 
     // generation 0: x uniform in the box (double, then rounded to float)
-    for (int jb = wave; jb * 4 < D; jb += 4)
+    for (int jb = wave; jb * 4 < D; jb += NW)
         for (int i = lane; i < np; i += 64) {
             const u32x4 w = draw(R.run_uid, seed32, 0, (uint32_t)i, TAG_INIT_X, (uint32_t)jb);
 #pragma unroll
@@ -213,12 +312,12 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
                 const int j = jb * 4 + e;
                 if (j < D) {
                     const float x = (float)((double)R.lb + ((double)R.ub - (double)R.lb) * u24d(word(w, e)));
-                    R.X[j * npp + i] = x;
-                    if (pso) { R.V[j * npp + i] = 0.f; R.P[j * npp + i] = x; }
+                    X[j * npp + i] = x;
+                    if (pso) { V[j * npp + i] = 0.f; P[j * npp + i] = x; }
                 }
             }
         }
-    __syncthreads();
+    t.sync();
 
     int64_t fe = 0;
     int gen = 0;
@@ -226,8 +325,8 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
     auto record = [&](const float *Y, const float *eY) {
         float pv;
         int pi;
-        const float before = sBest;
-        prefix_min(tid < np ? err_key(eY[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
+        const float before = sBestA[s];
+        prefix_min(t, tid < np ? err_key(eY[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
         if (tid < np && R.trace) {
             const int64_t c = fe + tid + 1;
             if (c % TRACE_EVERY == 0) {
@@ -237,110 +336,133 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
         }
         if (tid == 0) {
             const int lim = (int)min<int64_t>((int64_t)np, R.budget - fe);
-            sCopy = -1;
-            if (lim > 0 && sPv[lim - 1] < sBestB) { sBestB = sPv[lim - 1]; sCopy = sPi[lim - 1]; }
-            sBest = fminf(before, sPv[np - 1]);
+            sCopyA[s] = -1;
+            if (lim > 0 && sPv[lim - 1] < sBestBA[s]) { sBestBA[s] = sPv[lim - 1]; sCopyA[s] = sPi[lim - 1]; }
+            sBestA[s] = fminf(before, sPv[np - 1]);
         }
-        __syncthreads();
-        const int cp = sCopy;
+        t.sync();
+        const int cp = sCopyA[s];
         if (cp >= 0)
-            for (int j = tid; j < D; j += 256) R.bestx[j] = Y[j * npp + cp];
-        __syncthreads();
+            for (int j = tid; j < D; j += TS) R.bestx[j] = Y[j * npp + cp];
+        t.sync();
     };
     // gbest = argmin e(p), lowest index on ties
     auto global_best = [&]() {
         float pv;
         int pi;
-        prefix_min(tid < np ? err_key(R.eP[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
-        if (tid == 0) sG = sPi[255];
-        __syncthreads();
+        prefix_min(t, tid < np ? err_key(sEP[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
+        if (tid == 0) sGA[s] = sPi[TS - 1];
+        t.sync();
     };
     // dst[j][i] = src[j][i] for the individuals with sFlag[i] set
+    // (chunks of 8 rows: loads before stores)
     auto copy_flagged = [&](float *dst, const float *src) {
-        for (int j = wave; j < D; j += 4)
-            for (int i = lane; i < np; i += 64)
-                if (sFlag[i]) dst[j * npp + i] = src[j * npp + i];
-        __syncthreads();
+        constexpr int CP_CH = ONCHIP ? 1 : 8;
+        for (int j0 = wave * CP_CH; j0 < D; j0 += NW * CP_CH)
+            for (int i = lane; i < np; i += 64) {
+                const bool f = sFlag[i] != 0;
+                float v[CP_CH];
+#pragma unroll
+                for (int c = 0; c < CP_CH; ++c) v[c] = src[min(j0 + c, D - 1) * npp + i];
+#pragma unroll
+                for (int c = 0; c < CP_CH; ++c)
+                    if (f && j0 + c < D) dst[(j0 + c) * npp + i] = v[c];
+            }
+        t.sync();
     };
 
-    eval_pop<KS>(R, R.X, R.eX, sA, sO, sT, K);
-    __syncthreads();
-    record(R.X, R.eX);
+    eval_pop<KS, ONCHIP>(t, R, X, sEX, sA, sO, sT, K);
+    t.sync();
+    record(X, sEX);
     if (pso) {
-        if (tid < np) R.eP[tid] = R.eX[tid];
-        __syncthreads();
+        if (tid < np) sEP[tid] = sEX[tid];
+        t.sync();
         global_best();
     }
     fe = np;
 
     while (fe < R.budget) {
         ++gen;
-        const uint32_t t = (uint32_t)gen;
+        const uint32_t tg = (uint32_t)gen;
         if (pso) {
             // ---- PSO: update, evaluate, personal and global bests ----
-            const int g = sG;
-            for (int jb = wave; jb * 2 < D; jb += 4)
+            const int g = sGA[s];
+            // chunks of PSO_CH coordinate blocks: all loads of a chunk are
+            // issued before its stores, so a chunk costs one memory round trip
+            // (from LDS a round trip is short and one block at a time saves
+            // registers)
+            constexpr int PSO_CH = ONCHIP ? 1 : (KS <= 13 ? 4 : 2);
+            const int nb2 = (D + 1) / 2;
+            for (int jb0 = wave * PSO_CH; jb0 < nb2; jb0 += NW * PSO_CH)
                 for (int i = lane; i < np; i += 64) {
-                    const u32x4 wd = draw(R.run_uid, seed32, t, (uint32_t)i, TAG_PSO_R, (uint32_t)jb);
-                    float xj[2], vv[2], pj[2], pg[2];
+                    float xj[PSO_CH][2], vv[PSO_CH][2], pj[PSO_CH][2], pg[PSO_CH][2];
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int row = min(jb * 2 + e, D - 1) * npp;
-                        xj[e] = R.X[row + i];
-                        vv[e] = R.V[row + i];
-                        pj[e] = R.P[row + i];
-                        pg[e] = R.P[row + g];
-                    }
+                    for (int c = 0; c < PSO_CH; ++c)
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int j = jb * 2 + e;
-                        if (j < D) {
-                            const int row = j * npp;
-                            const float r1 = u24f(word(wd, 2 * e)), r2 = u24f(word(wd, 2 * e + 1));
-                            float vj = R.w * vv[e] + R.c1 * r1 * (pj[e] - xj[e]) + R.c2 * r2 * (pg[e] - xj[e]);
-                            vj = fminf(fmaxf(vj, -R.vmax), R.vmax);
-                            float xn = xj[e] + vj;
-                            if (xn < R.lb) { xn = R.lb; vj = 0.f; }
-                            else if (xn > R.ub) { xn = R.ub; vj = 0.f; }
-                            R.X[row + i] = xn;
-                            R.V[row + i] = vj;
+                        for (int e = 0; e < 2; ++e) {
+                            const int row = min((jb0 + c) * 2 + e, D - 1) * npp;
+                            xj[c][e] = X[row + i];
+                            vv[c][e] = V[row + i];
+                            pj[c][e] = P[row + i];
+                            pg[c][e] = P[row + g];
+                        }
+#pragma unroll
+                    for (int c = 0; c < PSO_CH; ++c) {
+                        const int jb = jb0 + c;
+                        if (jb >= nb2) break;
+                        const u32x4 wd = draw(R.run_uid, seed32, tg, (uint32_t)i, TAG_PSO_R, (uint32_t)jb);
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const int j = jb * 2 + e;
+                            if (j < D) {
+                                const int row = j * npp;
+                                const float r1 = u24f(word(wd, 2 * e)), r2 = u24f(word(wd, 2 * e + 1));
+                                float vj = R.w * vv[c][e] + R.c1 * r1 * (pj[c][e] - xj[c][e]) +
+                                           R.c2 * r2 * (pg[c][e] - xj[c][e]);
+                                vj = fminf(fmaxf(vj, -R.vmax), R.vmax);
+                                float xn = xj[c][e] + vj;
+                                if (xn < R.lb) { xn = R.lb; vj = 0.f; }
+                                else if (xn > R.ub) { xn = R.ub; vj = 0.f; }
+                                X[row + i] = xn;
+                                V[row + i] = vj;
+                            }
                         }
                     }
                 }
-            __syncthreads();
-            eval_pop<KS>(R, R.X, R.eX, sA, sO, sT, K);
-            __syncthreads();
-            record(R.X, R.eX);
+            t.sync();
+            eval_pop<KS, ONCHIP>(t, R, X, sEX, sA, sO, sT, K);
+            t.sync();
+            record(X, sEX);
             if (tid < np) {
-                const bool imp = err_key(R.eX[tid]) < err_key(R.eP[tid]);
-                if (imp) R.eP[tid] = R.eX[tid];
+                const bool imp = err_key(sEX[tid]) < err_key(sEP[tid]);
+                if (imp) sEP[tid] = sEX[tid];
                 sFlag[tid] = imp ? 1 : 0;
             }
-            __syncthreads();
-            copy_flagged(R.P, R.X);
+            t.sync();
+            copy_flagged(P, X);
             global_best();
         } else {
             // ---- DE rand/1/bin or SHADE current-to-pbest/1 ----
             if (shade) {
                 // ranking by (error, index): every key counts the keys below it
                 if (tid < np) {
-                    const uint32_t bits = __float_as_uint(err_key(R.eX[tid]));
+                    const uint32_t bits = __float_as_uint(err_key(sEX[tid]));
                     const uint32_t ord = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
                     sKey[tid] = ((unsigned long long)ord << 32) | (uint32_t)tid;
                 }
-                __syncthreads();
+                t.sync();
                 if (tid < np) {
                     const unsigned long long key = sKey[tid];
                     int rank = 0;
                     for (int q = 0; q < np; ++q) rank += sKey[q] < key ? 1 : 0;
                     sRank[rank] = tid;
                 }
-                __syncthreads();
+                t.sync();
             }
             if (tid < np) {
                 const int i = tid;
                 if (shade) {
-                    const ShadeDraw d = shade_draw(R.run_uid, seed32, t, i, np, D, R.H, R.pnum, sMF, sMCR);
+                    const ShadeDraw d = shade_draw(R.run_uid, seed32, tg, i, np, D, R.H, R.pnum, sMF, sMCR);
                     sF[i] = d.F;
                     sCR[i] = d.CR;
                     sFi[i] = d.F;
@@ -351,7 +473,7 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
                     sJr[i] = d.jrand;
                 } else {
                     int ia, ib, ic, jrand;
-                    de_donors(R.run_uid, seed32, t, i, np, D, ia, ib, ic, jrand);
+                    de_donors(R.run_uid, seed32, tg, i, np, D, ia, ib, ic, jrand);
                     sFi[i] = R.F;
                     sThr[i] = R.thr;
                     sDa[i] = ia;
@@ -360,42 +482,53 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
                     sJr[i] = jrand;
                 }
             }
-            __syncthreads();
-            for (int jb = wave; jb * 4 < D; jb += 4)
+            t.sync();
+            // chunks of DE_CH coordinate blocks, loads before stores (see PSO)
+            constexpr int DE_CH = ONCHIP ? 1 : (KS <= 13 ? 2 : 1);
+            const int nb4 = (D + 3) / 4;
+            for (int jb0 = wave * DE_CH; jb0 < nb4; jb0 += NW * DE_CH)
                 for (int i = lane; i < np; i += 64) {
-                    const u32x4 w = draw(R.run_uid, seed32, t, (uint32_t)i, TAG_CROSS, (uint32_t)jb);
                     const int ia = sDa[i], ib = sDb[i], ic = sDc[i], jrand = sJr[i];
                     const float Fi = sFi[i];
                     const uint32_t thr = sThr[i];
-                    float xi[4], xa[4], xb[4], xc[4];
+                    float xi[DE_CH][4], xa[DE_CH][4], xb[DE_CH][4], xc[DE_CH][4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int row = min(jb * 4 + e, D - 1) * npp;
-                        xi[e] = R.X[row + i];
-                        xa[e] = R.X[row + ia];
-                        xb[e] = R.X[row + ib];
-                        xc[e] = R.X[row + ic];
-                    }
+                    for (int c = 0; c < DE_CH; ++c)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int j = jb * 4 + e;
-                        if (j < D) {
-                            // SHADE: ic is the pbest individual, v = x + F (x_pbest - x) + F (x_r1 - x_r2)
-                            float v;
-                            if (shade) v = xi[e] + Fi * (xc[e] - xi[e]) + Fi * (xa[e] - xb[e]);
-                            else v = xa[e] + Fi * (xb[e] - xc[e]);
-                            bool m;
-                            R.U[j * npp + i] = cross_repair<float>(word(w, e), thr, j, jrand, v, xi[e], R.lb, R.ub, m);
+                        for (int e = 0; e < 4; ++e) {
+                            const int row = min((jb0 + c) * 4 + e, D - 1) * npp;
+                            xi[c][e] = X[row + i];
+                            xa[c][e] = X[row + ia];
+                            xb[c][e] = X[row + ib];
+                            xc[c][e] = X[row + ic];
+                        }
+#pragma unroll
+                    for (int c = 0; c < DE_CH; ++c) {
+                        const int jb = jb0 + c;
+                        if (jb >= nb4) break;
+                        const u32x4 w = draw(R.run_uid, seed32, tg, (uint32_t)i, TAG_CROSS, (uint32_t)jb);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int j = jb * 4 + e;
+                            if (j < D) {
+                                // SHADE: ic is the pbest individual, v = x + F (x_pbest - x) + F (x_r1 - x_r2)
+                                float v;
+                                if (shade) v = xi[c][e] + Fi * (xc[c][e] - xi[c][e]) + Fi * (xa[c][e] - xb[c][e]);
+                                else v = xa[c][e] + Fi * (xb[c][e] - xc[c][e]);
+                                bool m;
+                                U[j * npp + i] = cross_repair<float>(word(w, e), thr, j, jrand, v, xi[c][e], R.lb,
+                                                                     R.ub, m);
+                            }
                         }
                     }
                 }
-            __syncthreads();
-            eval_pop<KS>(R, R.U, R.eU, sA, sO, sT, K);
-            __syncthreads();
-            record(R.U, R.eU);
+            t.sync();
+            eval_pop<KS, ONCHIP>(t, R, U, sEU, sA, sO, sT, K);
+            t.sync();
+            record(U, sEU);
             double st[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum dl, dl CR, dl F^2, dl F, successes
             if (tid < np) {
-                const float ku = err_key(R.eU[tid]), kx = err_key(R.eX[tid]);
+                const float ku = err_key(sEU[tid]), kx = err_key(sEX[tid]);
                 if (shade && ku < kx) {
                     double dl = (double)kx - (double)ku;
                     if (!(dl <= 1e30)) dl = 1e30;
@@ -406,35 +539,36 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
                     st[4] = 1.0;
                 }
                 const bool rep = ku <= kx;
-                if (rep) R.eX[tid] = R.eU[tid];
+                if (rep) sEX[tid] = sEU[tid];
                 sFlag[tid] = rep ? 1 : 0;
             }
-            __syncthreads();
-            copy_flagged(R.X, R.U);
+            t.sync();
+            copy_flagged(X, U);
             if (shade) {
-                block_sums<5>(st, sRed);
+                team_sums<5>(t, st, sRed);
                 if (tid == 0 && st[4] > 0.0) {
-                    sMCR[sPos] = (float)(st[1] / st[0]);
-                    sMF[sPos] = (float)(st[2] / st[3]);
-                    sPos = (sPos + 1) % R.H;
+                    const int pos = sPosA[s];
+                    sMCR[pos] = (float)(st[1] / st[0]);
+                    sMF[pos] = (float)(st[2] / st[3]);
+                    sPosA[s] = (pos + 1) % R.H;
                 }
-                __syncthreads();
+                t.sync();
             }
         }
         fe += np;
     }
 
     // results; the best point is re-evaluated in double once below 1e-6
-    const float be = sBestB;
+    const float be = sBestBA[s];
     double e64 = (double)be;
     if (be < 1e-6f) {
         switch (R.func) {
-        case ELLIPSOID: e64 = check_f64<ELLIPSOID>(R, R.bestx, sZ, K); break;
-        case ROSENBROCK: e64 = check_f64<ROSENBROCK>(R, R.bestx, sZ, K); break;
-        case RASTRIGIN: e64 = check_f64<RASTRIGIN>(R, R.bestx, sZ, K); break;
-        case SCHWEFEL: e64 = check_f64<SCHWEFEL>(R, R.bestx, sZ, K); break;
-        case GRIEWANK: e64 = check_f64<GRIEWANK>(R, R.bestx, sZ, K); break;
-        default: e64 = check_f64<ACKLEY>(R, R.bestx, sZ, K); break;
+        case ELLIPSOID: e64 = check_f64<ELLIPSOID>(t, R, R.bestx, sZ, K); break;
+        case ROSENBROCK: e64 = check_f64<ROSENBROCK>(t, R, R.bestx, sZ, K); break;
+        case RASTRIGIN: e64 = check_f64<RASTRIGIN>(t, R, R.bestx, sZ, K); break;
+        case SCHWEFEL: e64 = check_f64<SCHWEFEL>(t, R, R.bestx, sZ, K); break;
+        case GRIEWANK: e64 = check_f64<GRIEWANK>(t, R, R.bestx, sZ, K); break;
+        default: e64 = check_f64<ACKLEY>(t, R, R.bestx, sZ, K); break;
         }
     }
     if (tid == 0) {
@@ -447,18 +581,22 @@ __global__ __launch_bounds__(256) void k_run(const RunDev *__restrict__ runs, ui
         o.reserved = 0;
     }
     if (R.best_x_out)
-        for (int j = tid; j < D; j += 256) R.best_x_out[(int64_t)R.out_index * R.max_dim + j] = (double)R.bestx[j];
+        for (int j = tid; j < D; j += TS) R.best_x_out[(int64_t)R.out_index * R.max_dim + j] = (double)R.bestx[j];
 }
 
-typedef void (*RunKernel)(const RunDev *, uint32_t, Consts);
+typedef void (*RunKernel)(const RunDev *, uint32_t, Consts, int);
 
 template <int KS>
-static RunKernel run_kernel() { return k_run<KS>; }
+static RunKernel run_kernel(bool onchip, bool wave)
+{
+    if (wave) return onchip ? k_run<KS, true, true> : k_run<KS, false, true>;
+    return onchip ? k_run<KS, true, false> : k_run<KS, false, false>;
+}
 
-static RunKernel run_table(int ks)
+static RunKernel run_table(int ks, bool onchip, bool wave)
 {
     switch (ks) {
-#define SEVO_KS_CASE(v) case v: return run_kernel<v>();
+#define SEVO_KS_CASE(v) case v: return run_kernel<v>(onchip, wave);
         SEVO_KS_CASE(1) SEVO_KS_CASE(2) SEVO_KS_CASE(3) SEVO_KS_CASE(4) SEVO_KS_CASE(5)
         SEVO_KS_CASE(6) SEVO_KS_CASE(7) SEVO_KS_CASE(8) SEVO_KS_CASE(9) SEVO_KS_CASE(10)
         SEVO_KS_CASE(11) SEVO_KS_CASE(12) SEVO_KS_CASE(13) SEVO_KS_CASE(14) SEVO_KS_CASE(15)
@@ -517,24 +655,75 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
     return SEVO_OK;
 }
 
+// Dynamic LDS that a workgroup of k_run<ks, on chip, team> may take: what
+// the device allows beside the kernel's own arrays, capped so that two
+// workgroups still fit a CU's 160 KB.  0 when not available.  Computed once
+// per process and kernel.
+static size_t onchip_limit(int ks, bool wave)
+{
+    static size_t cache[64][2][2] = {};   // [ks][wave] = {done, limit}
+    constexpr size_t CAP = 80 * 1024;
+    if (ks < 1 || ks >= 64) return 0;
+    size_t *c = cache[ks][wave ? 1 : 0];
+    if (c[0]) return c[1];
+    size_t lim = 0;
+    int dev = 0, maxblk = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&maxblk, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+        const void *k = (const void *)run_table(ks, true, wave);
+        hipFuncAttributes fa;
+        const size_t total = std::min((size_t)maxblk, CAP);
+        if (k && hipFuncGetAttributes(&fa, k) == hipSuccess && total > fa.sharedSizeBytes) {
+            const size_t want = total - fa.sharedSizeBytes;
+            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
+                lim = want;
+        }
+    }
+    (void)hipGetLastError();
+    c[0] = 1;
+    c[1] = lim;
+    return lim;
+}
+
 int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *results, float *trace,
               int64_t trace_len, double *best_x, int max_dim, hipStream_t stream)
 {
-    // workspace
+    // Team: runs of up to 64 individuals get one wave each (four runs of
+    // one instance per workgroup), larger ones a whole workgroup.
+    // Placement: a population that fits in the LDS left beside the kernel's
+    // own arrays stays on chip, the others use the workspace.  Results do
+    // not depend on either choice (the tests compare them); the variables
+    // SEVO_RUN_TEAM=block and SEVO_RUN_PLACEMENT=workspace force the
+    // alternatives.
+    const char *tv = std::getenv("SEVO_RUN_TEAM");
+    const bool force_block = tv && std::strcmp(tv, "block") == 0;
+    const char *pl = std::getenv("SEVO_RUN_PLACEMENT");
+    const bool force_ws = pl && std::strcmp(pl, "workspace") == 0;
+    std::vector<char> onchip(n), wave(n);
+    std::vector<size_t> dyn(n), off(n);
     size_t total = 0;
-    std::vector<size_t> off(n);
     for (int r = 0; r < n; ++r) {
         const int npp = (runs[r].np + 15) & ~15;
         const size_t D = runs[r].prob.dim;
+        const size_t nbuf = runs[r].algo == SEVO_ALGO_PSO ? 3 : 2;
+        wave[r] = !force_block && runs[r].np <= 64 ? 1 : 0;
+        dyn[r] = nbuf * D * npp;   // floats
+        const size_t per_wg = (wave[r] ? 4 : 1) * dyn[r] * sizeof(float);
+        onchip[r] = !force_ws && per_wg <= onchip_limit(ks_of((int)D), wave[r]) ? 1 : 0;
         off[r] = total;
-        total += 4 * D * npp + 3 * (size_t)npp + D;
+        total += (onchip[r] ? 0 : 4 * D * npp) + D;
         total = (total + 63) & ~(size_t)63;
     }
     float *ws = nullptr;
     int rc = ctx_ws(ctx).get(ctx, WS_RUN, total * sizeof(float), (void **)&ws);
     if (rc) return rc;
-    std::map<int, std::vector<RunDev>> groups;
-    std::map<int, std::vector<double>> cost;
+    // one launch per (dimension class, placement, team)
+    struct Group {
+        std::vector<RunDev> runs;
+        std::vector<double> cost;
+        size_t stride = 0;
+    };
+    std::map<int, Group> groups;
     for (int r = 0; r < n; ++r) {
         const sevo_run_desc &d = runs[r];
         InstanceView I;
@@ -562,38 +751,75 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.tab = I.tab;
         R.M64 = I.M64;
         float *b = ws + off[r];
-        const size_t DN = (size_t)R.dim * R.npp;
-        R.X = b; R.U = b + DN; R.V = b + 2 * DN; R.P = b + 3 * DN;
-        R.eX = b + 4 * DN; R.eU = R.eX + R.npp; R.eP = R.eU + R.npp; R.bestx = R.eP + R.npp;
+        if (onchip[r]) {
+            R.X = R.U = R.V = R.P = nullptr;
+            R.bestx = b;
+        } else {
+            const size_t DN = (size_t)R.dim * R.npp;
+            R.X = b; R.U = b + DN; R.V = b + 2 * DN; R.P = b + 3 * DN;
+            R.bestx = b + 4 * DN;
+        }
         R.res = results;
         R.trace = trace;
         R.trace_len = trace_len;
         R.best_x_out = best_x;
         R.max_dim = max_dim;
         R.out_index = r;
-        const int ks = ks_of(R.dim);
-        groups[ks].push_back(R);
-        cost[ks].push_back((double)d.budget * R.dim * R.dim);
+        Group &G = groups[ks_of(R.dim) * 4 + onchip[r] * 2 + wave[r]];
+        G.runs.push_back(R);
+        G.cost.push_back((double)d.budget * R.dim * R.dim);
+        if (onchip[r]) G.stride = std::max(G.stride, dyn[r]);
     }
     const int ng = (int)groups.size();
     std::vector<hipStream_t> ss(ng);
     if ((rc = fork_streams(ctx, stream, ng, ss.data()))) return rc;
     int g = 0;
     for (auto &kv : groups) {
-        std::vector<RunDev> &v = kv.second;
-        // longest runs first, so the tail is short
-        std::vector<int> order(v.size());
-        for (size_t i = 0; i < v.size(); ++i) order[i] = (int)i;
-        const std::vector<double> &c = cost[kv.first];
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c[a] > c[b]; });
-        std::vector<char> blob(v.size() * sizeof(RunDev));
-        for (size_t i = 0; i < v.size(); ++i) std::memcpy(blob.data() + i * sizeof(RunDev), &v[order[i]], sizeof(RunDev));
+        const bool gon = (kv.first & 2) != 0, gwave = (kv.first & 1) != 0;
+        Group &G = kv.second;
+        std::vector<RunDev> launch;
+        std::vector<int> order(G.runs.size());
+        for (size_t i = 0; i < G.runs.size(); ++i) order[i] = (int)i;
+        if (!gwave) {
+            // longest runs first, so the tail is short
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return G.cost[a] > G.cost[b]; });
+            for (int i : order) launch.push_back(G.runs[i]);
+        } else {
+            // workgroups of four runs of one instance (empty slots have np = 0),
+            // workgroups with the longest runs first
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                if (G.runs[a].Mfrag != G.runs[b].Mfrag) return G.runs[a].Mfrag < G.runs[b].Mfrag;
+                return G.cost[a] > G.cost[b];
+            });
+            std::vector<std::pair<double, std::vector<int>>> wgs;
+            for (size_t i = 0; i < order.size();) {
+                std::vector<int> m;
+                const float *inst = G.runs[order[i]].Mfrag;
+                while (i < order.size() && m.size() < 4 && G.runs[order[i]].Mfrag == inst) m.push_back(order[i++]);
+                wgs.emplace_back(G.cost[m[0]], m);
+            }
+            std::stable_sort(wgs.begin(), wgs.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+            for (const auto &w : wgs)
+                for (int k = 0; k < 4; ++k) {
+                    if (k < (int)w.second.size()) {
+                        launch.push_back(G.runs[w.second[k]]);
+                    } else {
+                        RunDev E = G.runs[w.second[0]];   // same instance, no work
+                        E.np = 0;
+                        launch.push_back(E);
+                    }
+                }
+        }
+        const unsigned grid = (unsigned)(gwave ? launch.size() / 4 : launch.size());
+        std::vector<char> blob(launch.size() * sizeof(RunDev));
+        std::memcpy(blob.data(), launch.data(), blob.size());
         const void *d = nullptr;
         int slot;
         if ((rc = stage_blob(ctx, blob, ss[g], &d, &slot))) return rc;
-        RunKernel k = run_table(kv.first);
-        hipLaunchKernelGGL(k, dim3((unsigned)v.size()), dim3(256), 0, ss[g], (const RunDev *)d,
-                           ctx_seed32(ctx), ctx_consts(ctx));
+        RunKernel k = run_table(kv.first / 4, gon, gwave);
+        const size_t shm = gon ? (gwave ? 4 : 1) * G.stride * sizeof(float) : 0;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(256), shm, ss[g], (const RunDev *)d, ctx_seed32(ctx),
+                           ctx_consts(ctx), (int)G.stride);
         if (hipGetLastError() != hipSuccess) return set_error(ctx, SEVO_EDEVICE, "run kernel launch failed");
         if ((rc = finish_slot(ctx, slot, ss[g]))) return rc;
         ++g;

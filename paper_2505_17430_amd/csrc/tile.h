@@ -71,14 +71,15 @@ __device__ __forceinline__ void fold_rows(AccF (&acc)[CT], const floatx4 (&zc)[C
     }
 }
 
-// Rotation and objective of one wave's 16*CT points.  The row tiles are
+// Rotation and objective of one wave's 16*CT points, errors stored to E
+// (global memory, or LDS in the fused run kernels).  The row tiles are
 // software-pipelined: the MFMA chain of tile rt + 1 is issued before the
 // objective of tile rt is folded, so matrix-core and vector work of one wave
 // overlap, and z never leaves the registers.
-template <int FUNC, int KS, int CT>
+template <int FUNC, int KS, int CT, typename EPtr>
 __device__ __forceinline__ void tile_body(const float (&b)[KS][CT], const float *sA, const float *sT,
                                           int lane, int dim, int n, int p0,
-                                          const SchwefelConst<float> &K, SEVO_GLOBAL float *__restrict__ E)
+                                          const SchwefelConst<float> &K, EPtr E)
 {
     constexpr int RT = (KS + 3) / 4;
     AccF acc[CT];
@@ -141,6 +142,20 @@ __device__ __forceinline__ void load_raw(float (&raw)[KS][CT], const SEVO_GLOBAL
             const uint32_t o = ks == KS - 1 ? offl[c] : off[c];
             raw[ks][c] = *reinterpret_cast<const SEVO_GLOBAL float *>(row + o);
         }
+    }
+}
+
+// The same loads from a population held in LDS (fused runs whose state
+// fits on chip): clamped row and point indices, no address tricks needed.
+template <int KS, int CT>
+__device__ __forceinline__ void load_raw_lds(float (&raw)[KS][CT], const float *X, int ld, int dim, int n,
+                                             int p0, int kq, int pc)
+{
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = min(ks * 4 + kq, dim - 1);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) raw[ks][c] = X[k * ld + min(p0 + c * 16 + pc, n - 1)];
     }
 }
 

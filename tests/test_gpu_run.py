@@ -185,6 +185,43 @@ def test_fused_mixed_batch_matches_single_runs(ctx):
         assert np.array_equal(bx1[0], bxb[k])
 
 
+def test_fused_placement_does_not_change_results(ctx, monkeypatch):
+    """Populations kept in LDS and populations in the workspace give the
+    same bits: results, traces and best points."""
+    descs = [desc(S.ALGO_DE, S.RASTRIGIN, 10, 50, 3000, uid=21),
+             desc(S.ALGO_PSO, S.GRIEWANK, 50, 40, 4000, uid=22),
+             desc(S.ALGO_SHADE, S.ROSENBROCK, 30, 200, 6000, uid=23),
+             desc(S.ALGO_SHADE, S.SCHWEFEL, 100, 200, 2000, uid=24),
+             desc(S.ALGO_PSO, S.ACKLEY, 10, 7, 500, uid=25)]
+    r1, t1, b1 = gpu_run(ctx, descs, trace_len=30, max_dim=100)
+    monkeypatch.setenv("SEVO_RUN_PLACEMENT", "workspace")
+    r2, t2, b2 = gpu_run(ctx, descs, trace_len=30, max_dim=100)
+    monkeypatch.delenv("SEVO_RUN_PLACEMENT")
+    assert r1 == r2
+    assert np.array_equal(t1, t2, equal_nan=True)
+    assert np.array_equal(b1, b2)
+
+
+def test_fused_team_does_not_change_results(ctx, monkeypatch):
+    """Runs of up to 64 individuals carried by one wave each (four runs of an
+    instance per workgroup, here 4 + 4 + 1 plus other instances) give the
+    same bits as the same runs carried by whole workgroups."""
+    descs = [desc(algo, S.RASTRIGIN, 30, np_, 2500, uid=40 + k)
+             for k, (algo, np_) in enumerate([(S.ALGO_DE, 50), (S.ALGO_PSO, 40), (S.ALGO_SHADE, 64),
+                                              (S.ALGO_DE, 4), (S.ALGO_PSO, 1), (S.ALGO_SHADE, 20),
+                                              (S.ALGO_DE, 33), (S.ALGO_PSO, 64), (S.ALGO_DE, 17)])]
+    descs += [desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=60, inst=3),
+              desc(S.ALGO_DE, S.ELLIPSOID, 100, 24, 1500, uid=61, inst=1),
+              desc(S.ALGO_SHADE, S.GRIEWANK, 50, 100, 3000, uid=62, inst=2)]
+    r1, t1, b1 = gpu_run(ctx, descs, trace_len=20, max_dim=100)
+    monkeypatch.setenv("SEVO_RUN_TEAM", "block")
+    r2, t2, b2 = gpu_run(ctx, descs, trace_len=20, max_dim=100)
+    monkeypatch.delenv("SEVO_RUN_TEAM")
+    assert r1 == r2
+    assert np.array_equal(t1, t2, equal_nan=True)
+    assert np.array_equal(b1, b2)
+
+
 def test_run_rejects_bad_arguments(ctx):
     res = torch.zeros(64, dtype=torch.uint8, device="cuda")
     with pytest.raises(S.SevoError):
