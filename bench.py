@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
                          "c4: batched SHADE; c5: D=1000 evaluation; copy: 512 MiB device copy "
@@ -160,6 +161,12 @@ def main():
     torch.cuda.synchronize()
     n_evals = sum(g[3] for g in groups)
     bytes_in = sum(g[3] * (4 * g[1] + 4) for g in groups)
+    # launch shapes chosen by the library's autotuner on the first replica
+    # (setup, outside the timed region; the choice does not change results)
+    tuned = {}
+    if not a.no_tune:
+        for d in W.C2_DIMS:
+            tuned.update(ctx.tune_evaluate(reps[0][d][1], precision=prec, stream=stream))
 
     def step(rep, ev=None):
         for d in W.C2_DIMS:
@@ -221,6 +228,7 @@ def main():
                                "rotation, compensated FP32 objective",
                    "evals_per_step": n_evals, "input_bytes_per_step": bytes_in,
                    "replicas": a.replicas, "precision": a.precision,
+                   "tiles_per_workgroup": {str(k): v for k, v in sorted(tuned.items())} or "resident grid",
                    "tolerance": "|de| <= max(1e-6, 1e-5 e) vs FP64 oracle"},
         "roofline": roof,
     }

@@ -158,6 +158,18 @@ typedef struct {
 int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
                         int32_t precision, void *stream);
 
+/* Autotuning of the batched evaluation (optional).  For every dimension
+ * class (k-steps ceil(D/4), D <= 120) present in `items`, times the launch
+ * shapes that cannot change any result -- the resident persistent grid and
+ * 1, 2, 3, 4, 6 or 8 tiles of 64-128 points per workgroup -- on these items
+ * (their err_out buffers are written, with the values sevo_evaluate_batch
+ * gives), and keeps the fastest in the context for later calls.
+ *   chosen  optional host [64]: per class, the tiles per workgroup chosen
+ *           (0 = resident grid), -1 for classes not present.
+ * Synchronises `stream`.  FP64 has nothing to tune (returns 0). */
+int sevo_tune_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items, int32_t precision,
+                       void *stream, int32_t *chosen);
+
 /* ---- one generation at a time ---- */
 
 /* State of `n_runs` runs of one (problem, instance): run r uses Philox key

@@ -37,7 +37,7 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
 // workgroups are renumbered per XCD, so an XCD works through a contiguous
 // stretch of items and their rotations stay in that XCD's L2.
 template <int KS, int CT>
-__global__ __launch_bounds__(256, 3) void k_eval_small(const EvalDesc *__restrict__ items, int n_items,
+__global__ __launch_bounds__(256, CT == 1 ? 3 : 2) void k_eval_small(const EvalDesc *__restrict__ items, int n_items,
                                                     int total_tiles, int grid, Consts K)
 {
     constexpr int RT = (KS + 3) / 4;
@@ -100,7 +100,10 @@ __global__ __launch_bounds__(256, 3) void k_eval_small(const EvalDesc *__restric
 
 // Points per wave: two 16-point column tiles while the coordinates fit
 // comfortably in registers, one for the larger dimensions.
-constexpr int ct_for(int ks) { return ks <= 8 ? 2 : 1; }
+#ifndef SEVO_CT_LARGE
+#define SEVO_CT_LARGE 1
+#endif
+constexpr int ct_for(int ks) { return ks <= 8 ? 2 : SEVO_CT_LARGE; }
 
 int small_tile_points(int ks) { return 64 * ct_for(ks); }
 

@@ -149,7 +149,8 @@ struct sevo_ctx {
     int next_slot = 0;
     int last_slot = -1;
     Consts consts;
-    int tiles_per_block = 0;     // 0 = automatic
+    int tiles_per_block = 0;     // SEVO_TILES_PER_BLOCK override; 0 = none
+    int tuned_tpb[64] = {};      // sevo_tune_evaluate's choice per k-step class; 0 = resident grid
     sevo::Workspace ws;
     std::vector<hipStream_t> streams;   // internal, default priority
     std::vector<hipEvent_t> fork_ev;    // one per internal stream + the fork event
@@ -354,16 +355,17 @@ int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
     return SEVO_OK;
 }
 
-// Workgroups of a persistent small-D launch: as many as the GPU holds at
-// once (times SEVO_TILES_PER_BLOCK^-1 when that override is set, for tuning),
-// never more than there are tiles.
+// Workgroups of a small-D launch: as many as the GPU holds at once, or
+// tiles / tpb for a tiles-per-workgroup choice (the SEVO_TILES_PER_BLOCK
+// override, else the autotuner's), never more than there are tiles.
 int small_grid(sevo_ctx *ctx, int ks, int tiles)
 {
     static std::map<int, int> resident;
     auto itr = resident.find(ks);
     if (itr == resident.end()) itr = resident.emplace(ks, small_resident_blocks(ks)).first;
     long g = itr->second;
-    if (ctx->tiles_per_block > 0) g = (tiles + ctx->tiles_per_block - 1) / ctx->tiles_per_block;
+    const int tpb = ctx->tiles_per_block > 0 ? ctx->tiles_per_block : (ks < 64 ? ctx->tuned_tpb[ks] : 0);
+    if (tpb > 0) g = (tiles + tpb - 1) / tpb;
     return (int)std::max<long>(1, std::min<long>(g, tiles));
 }
 
@@ -389,6 +391,8 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
         else if (d.dim <= SMALL_D_MAX) small[ks_of(d.dim)].push_back(d);
         else large.push_back(d);
     }
+    // (the launches stay in order on the caller's stream: measured, running
+    // the classes concurrently on internal streams was slower)
     for (auto &kv : small) {
         std::vector<EvalDesc> &v = kv.second;
         const int ks = kv.first, tp = small_tile_points(ks);
@@ -710,15 +714,10 @@ static int check_precision(sevo_ctx *ctx, int precision)
     return SEVO_OK;
 }
 
-int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
-                        int32_t precision, void *stream)
+static int build_items(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
+                       std::vector<std::pair<EvalDesc, int>> &v)
 {
-    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
-    int rc = check_precision(ctx, precision);
-    if (rc) return rc;
-    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, SEVO_EINVAL, "bad item list");
-    DeviceGuard g(ctx->device);
-    std::vector<std::pair<EvalDesc, int>> v;
+    int rc;
     v.reserve(n_items);
     for (int i = 0; i < n_items; ++i) {
         const sevo_eval_item &it = items[i];
@@ -744,7 +743,75 @@ int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_it
         d.dim = it.prob.dim;
         v.emplace_back(d, i);
     }
+    return SEVO_OK;
+}
+
+int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
+                        int32_t precision, void *stream)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    int rc = check_precision(ctx, precision);
+    if (rc) return rc;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, SEVO_EINVAL, "bad item list");
+    DeviceGuard g(ctx->device);
+    std::vector<std::pair<EvalDesc, int>> v;
+    if ((rc = build_items(ctx, items, n_items, v))) return rc;
     return eval_items(ctx, v, precision, (hipStream_t)stream);
+}
+
+int sevo_tune_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items, int32_t precision,
+                       void *stream, int32_t *chosen)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    int rc = check_precision(ctx, precision);
+    if (rc) return rc;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, SEVO_EINVAL, "bad item list");
+    DeviceGuard g(ctx->device);
+    std::vector<std::pair<EvalDesc, int>> v;
+    if ((rc = build_items(ctx, items, n_items, v))) return rc;
+    if (chosen)
+        for (int k = 0; k < 64; ++k) chosen[k] = -1;
+    if (precision == SEVO_FP64) return SEVO_OK;   // one thread per point: nothing to choose
+    std::map<int, std::vector<std::pair<EvalDesc, int>>> by_ks;
+    for (const auto &pr : v)
+        if (pr.first.dim <= SMALL_D_MAX) by_ks[ks_of(pr.first.dim)].push_back(pr);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    const int saved_override = ctx->tiles_per_block;
+    ctx->tiles_per_block = 0;
+    // candidates: the resident grid (0) and fixed tiles per workgroup; every
+    // candidate computes the same values, so the outputs are simply rewritten
+    const int cand[] = {0, 1, 2, 3, 4, 6, 8};
+    for (auto &kv : by_ks) {
+        const int ks = kv.first;
+        float best = 0.f;
+        int best_tpb = 0;
+        for (int c : cand) {
+            ctx->tuned_tpb[ks] = c;
+            if ((rc = eval_items(ctx, kv.second, precision, st))) break;   // warm-up
+            float ms_min = 0.f;
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                if (hipEventRecord(e0, st) != hipSuccess) rc = fail(ctx, SEVO_EDEVICE, "event record failed");
+                if (!rc) rc = eval_items(ctx, kv.second, precision, st);
+                if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(ctx, SEVO_EDEVICE, "event record failed");
+                if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(ctx, SEVO_EDEVICE, "event sync failed");
+                float ms = 0.f;
+                if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(ctx, SEVO_EDEVICE, "event time failed");
+                if (!rc && (rep == 0 || ms < ms_min)) ms_min = ms;
+            }
+            if (rc) break;
+            if (c == cand[0] || ms_min < best) { best = ms_min; best_tpb = c; }
+        }
+        if (rc) break;
+        ctx->tuned_tpb[ks] = best_tpb;
+        if (chosen) chosen[ks] = best_tpb;
+    }
+    ctx->tiles_per_block = saved_override;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int sevo_evaluate(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance, const void *x,

@@ -106,6 +106,7 @@ def lib():
     L.sevo_generate_instance.argtypes = [i32, i32, u32, u64, vp, vp]
     L.sevo_evaluate.argtypes = [vp, C.POINTER(Problem), u32, vp, i64, i32, vp, i32, vp]
     L.sevo_evaluate_batch.argtypes = [vp, C.POINTER(EvalItem), i32, i32, vp]
+    L.sevo_tune_evaluate.argtypes = [vp, C.POINTER(EvalItem), i32, i32, vp, C.POINTER(i32)]
     L.sevo_de_step.argtypes = [vp, C.POINTER(Problem), u32, C.POINTER(DEState),
                                C.POINTER(DEParams), i32, vp]
     L.sevo_pso_step.argtypes = [vp, C.POINTER(Problem), u32, C.POINTER(PSOState),
@@ -225,6 +226,14 @@ class Context:
         """items: list of (prob, inst, x, err[, n, ld]) or a prepare_batch() result."""
         arr = items if isinstance(items, C.Array) else self.prepare_batch(items)
         self._check(self._L.sevo_evaluate_batch(self._h, arr, len(arr), precision, _stream(stream)))
+
+    def tune_evaluate(self, items, precision=FP32, stream=None):
+        """Autotune the evaluation launch shape on these items; returns
+        {k-step class: tiles per workgroup (0 = resident grid)}."""
+        arr = items if isinstance(items, C.Array) else self.prepare_batch(items)
+        chosen = (C.c_int32 * 64)()
+        self._check(self._L.sevo_tune_evaluate(self._h, arr, len(arr), precision, _stream(stream), chosen))
+        return {k: chosen[k] for k in range(64) if chosen[k] >= 0}
 
     def de_step(self, prob, inst, state: DEState, F, CR, precision=FP32, stream=None):
         self._check(self._L.sevo_de_step(self._h, C.byref(prob), inst, C.byref(state),

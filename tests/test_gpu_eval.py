@@ -170,6 +170,47 @@ def test_batch_equals_single_and_is_deterministic(ctx):
         assert np.array_equal(single, b[:n].astype(np.float64))   # same kernel, same bits
 
 
+def test_launch_shape_and_autotune_do_not_change_results(ctx, monkeypatch):
+    """Every tiles-per-workgroup choice (and the autotuner's) computes the same
+    bits; the tuner reports a choice for each dimension class present."""
+    groups = [(0, 10, 0, 5100), (2, 30, 1, 777), (3, 50, 2, 5100), (5, 100, 3, 2049), (1, 100, 4, 33)]
+    errs, items = [], []
+    for (f, d, k, n) in groups:
+        xd = torch.from_numpy(W.uniform_points(W.group_seed(f, d, k, 11), d, n)).cuda()
+        e = torch.zeros(n, device="cuda")
+        errs.append(e)
+        items.append((S.problem(f, d), k, xd, e))
+    arr = S.Context.prepare_batch(items)
+
+    def outputs():
+        for e in errs:
+            e.fill_(float("nan"))
+        ctx.evaluate_batch(arr)
+        torch.cuda.synchronize()
+        return [e.cpu().numpy().copy() for e in errs]
+
+    ref = outputs()
+    for tpb in ("1", "2", "3", "8"):
+        monkeypatch.setenv("SEVO_TILES_PER_BLOCK", tpb)
+        # the override is read when a context is created
+        c2 = S.Context(0, W.BASE_SEED, W.INSTANCE_SEED)
+        for e in errs:
+            e.fill_(float("nan"))
+        c2.evaluate_batch(arr)
+        torch.cuda.synchronize()
+        say("  tiles per block", tpb)
+        for a, b in zip(ref, [e.cpu().numpy() for e in errs]):
+            assert np.array_equal(a, b)
+        c2.close()
+    monkeypatch.delenv("SEVO_TILES_PER_BLOCK")
+    chosen = ctx.tune_evaluate(arr)
+    say("  tuned", chosen)
+    assert set(chosen) == {3, 8, 13, 25}
+    assert all(v in (0, 1, 2, 3, 4, 6, 8) for v in chosen.values())
+    for a, b in zip(ref, outputs()):
+        assert np.array_equal(a, b)
+
+
 def test_invalid_arguments(ctx):
     x = torch.zeros((10, 4), device="cuda")
     e = torch.zeros(4, device="cuda")
