@@ -693,12 +693,21 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
     // Placement: a population that fits in the LDS left beside the kernel's
     // own arrays stays on chip, the others use the workspace.  Results do
     // not depend on either choice (the tests compare them); the variables
-    // SEVO_RUN_TEAM=block and SEVO_RUN_PLACEMENT=workspace force the
+    // SEVO_RUN_TEAM=block|wave and SEVO_RUN_PLACEMENT=workspace force the
     // alternatives.
     const char *tv = std::getenv("SEVO_RUN_TEAM");
     const bool force_block = tv && std::strcmp(tv, "block") == 0;
     const char *pl = std::getenv("SEVO_RUN_PLACEMENT");
     const bool force_ws = pl && std::strcmp(pl, "workspace") == 0;
+    // Wave teams pay off once a dimension class has enough small runs to
+    // fill the GPU with four-run workgroups; a few runs go faster with a
+    // whole workgroup each (SEVO_RUN_TEAM=wave forces wave teams).
+    const bool force_wave = tv && std::strcmp(tv, "wave") == 0;
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    std::map<int, int> small_in_class;
+    for (int r = 0; r < n; ++r)
+        if (runs[r].np <= 64) ++small_in_class[ks_of(runs[r].prob.dim)];
     std::vector<char> onchip(n), wave(n);
     std::vector<size_t> dyn(n), off(n);
     size_t total = 0;
@@ -706,7 +715,8 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         const int npp = (runs[r].np + 15) & ~15;
         const size_t D = runs[r].prob.dim;
         const size_t nbuf = runs[r].algo == SEVO_ALGO_PSO ? 3 : 2;
-        wave[r] = !force_block && runs[r].np <= 64 ? 1 : 0;
+        const bool many = small_in_class[ks_of((int)D)] >= 4 * cus;
+        wave[r] = !force_block && runs[r].np <= 64 && (many || force_wave) ? 1 : 0;
         dyn[r] = nbuf * D * npp;   // floats
         const size_t per_wg = (wave[r] ? 4 : 1) * dyn[r] * sizeof(float);
         onchip[r] = !force_ws && per_wg <= onchip_limit(ks_of((int)D), wave[r]) ? 1 : 0;

@@ -213,6 +213,7 @@ def test_fused_team_does_not_change_results(ctx, monkeypatch):
     descs += [desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=60, inst=3),
               desc(S.ALGO_DE, S.ELLIPSOID, 100, 24, 1500, uid=61, inst=1),
               desc(S.ALGO_SHADE, S.GRIEWANK, 50, 100, 3000, uid=62, inst=2)]
+    monkeypatch.setenv("SEVO_RUN_TEAM", "wave")
     r1, t1, b1 = gpu_run(ctx, descs, trace_len=20, max_dim=100)
     monkeypatch.setenv("SEVO_RUN_TEAM", "block")
     r2, t2, b2 = gpu_run(ctx, descs, trace_len=20, max_dim=100)
