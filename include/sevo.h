@@ -273,6 +273,41 @@ int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t p
              sevo_run_result *results, float *trace, int64_t trace_len,
              double *best_x, int32_t max_dim, void *stream);
 
+/* ---- plans: work prepared once, then enqueued with launches only ----
+ *
+ * A plan holds everything a call needs on the device -- instances,
+ * descriptor tables, workspace and launch shapes -- so that enqueueing it
+ * allocates nothing, copies nothing and never waits on the host.  That makes
+ * sevo_plan_launch safe to capture into a HIP graph (stream capture) and to
+ * replay the graph, and cheap to call in a loop.  The buffers named when the
+ * plan was made (points, errors, results, traces) are read and written by
+ * every launch and must stay allocated while the plan is used; their
+ * contents may change between launches.  Launches of one plan must not
+ * overlap in time (they share the plan's workspace); different plans may.
+ * A plan belongs to its context and must be destroyed before it. */
+typedef struct sevo_plan sevo_plan;   /* opaque, library-owned */
+
+/* The evaluation of `items`, as sevo_evaluate_batch (launch shapes: the
+ * context's autotuned ones, else the defaults).  Synchronous. */
+int sevo_plan_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items, int32_t precision,
+                       sevo_plan **out);
+
+/* Whole runs, as sevo_run with precision SEVO_FP32 (the persistent fused
+ * kernels; the double-precision path is a host loop of launches and has no
+ * plan: SEVO_EUNSUPPORTED).  Every launch restarts the runs from generation
+ * 0 and rewrites results, trace and best_x.  Synchronous. */
+int sevo_plan_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+                  sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
+                  int32_t max_dim, sevo_plan **out);
+
+/* Enqueue the plan's kernels on `stream` (the context's internal streams
+ * join through events when a plan has concurrent launches).  Asynchronous. */
+int sevo_plan_launch(sevo_plan *plan, void *stream);
+
+/* Free the plan's device memory (waits for the device first).  NULL is a
+ * no-op. */
+int sevo_plan_destroy(sevo_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

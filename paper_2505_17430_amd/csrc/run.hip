@@ -780,9 +780,12 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         G.cost.push_back((double)d.budget * R.dim * R.dim);
         if (onchip[r]) G.stride = std::max(G.stride, dyn[r]);
     }
+    // the groups run concurrently, one internal stream each (a plan records
+    // the stream index and forks when it is launched)
+    const bool recording = ctx_recording(ctx) != nullptr;
     const int ng = (int)groups.size();
-    std::vector<hipStream_t> ss(ng);
-    if ((rc = fork_streams(ctx, stream, ng, ss.data()))) return rc;
+    std::vector<hipStream_t> ss(ng, stream);
+    if (!recording && (rc = fork_streams(ctx, stream, ng, ss.data()))) return rc;
     int g = 0;
     for (auto &kv : groups) {
         const bool gon = (kv.first & 2) != 0, gwave = (kv.first & 1) != 0;
@@ -826,18 +829,46 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         const void *d = nullptr;
         int slot;
         if ((rc = stage_blob(ctx, blob, ss[g], &d, &slot))) return rc;
-        RunKernel k = run_table(kv.first / 4, gon, gwave);
         const size_t shm = gon ? (gwave ? 4 : 1) * G.stride * sizeof(float) : 0;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(256), shm, ss[g], (const RunDev *)d, ctx_seed32(ctx),
-                           ctx_consts(ctx), (int)G.stride);
-        if (hipGetLastError() != hipSuccess) return set_error(ctx, SEVO_EDEVICE, "run kernel launch failed");
+        const Launch L{L_RUN, d, (int)launch.size(), kv.first / 4, 0, (int)grid, gon, gwave, shm, (int)G.stride, g};
+        if ((rc = emit_launch(ctx, L, ss[g]))) return rc;
         if ((rc = finish_slot(ctx, slot, ss[g]))) return rc;
         ++g;
     }
-    return join_streams(ctx, stream, ng, ss.data());
+    return recording ? SEVO_OK : join_streams(ctx, stream, ng, ss.data());
 }
 
 }  // namespace
+
+hipError_t sevo::exec_run_launch(const Launch &L, hipStream_t stream, uint32_t seed32, const Consts &k)
+{
+    RunKernel kern = run_table(L.ks, L.flag, L.wave);
+    if (!kern) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(256), L.shm, stream, (const RunDev *)L.d, seed32, k,
+                       L.stride);
+    return hipGetLastError();
+}
+
+extern "C" int sevo_plan_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+                             sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
+                             int32_t max_dim, sevo_plan **out)
+{
+    if (!ctx) return set_error(nullptr, SEVO_EINVAL, "ctx is NULL");
+    if (!out) return set_error(ctx, SEVO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!results) return set_error(ctx, SEVO_EINVAL, "results is NULL");
+    int rc = validate_runs(ctx, runs, n_runs, precision, trace_len, trace, best_x, max_dim);
+    if (rc) return rc;
+    if (precision != SEVO_FP32) return set_error(ctx, SEVO_EUNSUPPORTED, "plans run the FP32 fused path only");
+    DeviceScope dg(ctx);
+    for (int r = 0; r < n_runs; ++r) {   // instances are made before recording
+        InstanceView I;
+        if ((rc = lookup_instance(ctx, &runs[r].prob, runs[r].instance, &I))) return rc;
+    }
+    if ((rc = plan_begin(ctx))) return rc;
+    rc = run_fused(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, nullptr);
+    return plan_finish(ctx, rc, out);
+}
 
 extern "C" int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
                         sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,

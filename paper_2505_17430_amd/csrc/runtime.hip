@@ -152,8 +152,17 @@ struct sevo_ctx {
     int tiles_per_block = 0;     // SEVO_TILES_PER_BLOCK override; 0 = none
     int tuned_tpb[64] = {};      // sevo_tune_evaluate's choice per k-step class; 0 = resident grid
     sevo::Workspace ws;
+    sevo_plan *rec = nullptr;           // plan being built (calls record instead of launching)
     std::vector<hipStream_t> streams;   // internal, default priority
     std::vector<hipEvent_t> fork_ev;    // one per internal stream + the fork event
+};
+
+// A prepared call: plan-owned device memory and the launches to enqueue.
+struct sevo_plan {
+    sevo_ctx *ctx = nullptr;
+    std::vector<void *> dev;
+    std::vector<sevo::Launch> launches;
+    int lanes = 1;
 };
 
 static std::string g_create_error;
@@ -297,6 +306,15 @@ int stage_bytes(sevo_ctx *ctx, const std::vector<char> &blob, hipStream_t stream
                 int *slot_out)
 {
     const size_t n = blob.size();
+    if (ctx->rec) {   // building a plan: the table gets device memory of its own
+        void *d = nullptr;
+        int rc = sevo::plan_alloc(ctx, n, &d);
+        if (rc) return rc;
+        HIP_TRY(ctx, hipMemcpy(d, blob.data(), n, hipMemcpyHostToDevice));
+        *d_out = d;
+        *slot_out = -1;
+        return SEVO_OK;
+    }
     for (int k = 0; k < (int)ctx->slots.size(); ++k) {
         DescSlot &s = ctx->slots[k];
         if (s.used == n && s.valid && std::memcmp(s.h, blob.data(), n) == 0) {
@@ -351,6 +369,7 @@ int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t s
 
 int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
 {
+    if (slot < 0) return SEVO_OK;   // plan-owned table
     HIP_TRY(ctx, hipEventRecord(ctx->slots[slot].done, stream));
     return SEVO_OK;
 }
@@ -407,7 +426,8 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
         int slot;
         int rc = stage_descs(ctx, v, stream, &dd, &slot);
         if (rc) return rc;
-        HIP_TRY(ctx, launch_eval_small(dd, (int)v.size(), ks, tiles, grid, ctx->consts, stream));
+        if ((rc = emit_launch(ctx, Launch{L_SMALL, dd, (int)v.size(), ks, tiles, grid, false, false, 0, 0, 0}, stream)))
+            return rc;
         if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     }
     if (!f64.empty()) {
@@ -421,7 +441,8 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
         int slot;
         int rc = stage_descs(ctx, f64, stream, &dd, &slot);
         if (rc) return rc;
-        HIP_TRY(ctx, launch_eval_f64(dd, (int)f64.size(), blocks, ctx->consts, stream));
+        if ((rc = emit_launch(ctx, Launch{L_F64, dd, (int)f64.size(), 0, blocks, 0, false, false, 0, 0, 0}, stream)))
+            return rc;
         if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     }
     if (!large.empty()) {
@@ -456,7 +477,8 @@ int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStre
     const EvalDesc *dd;
     int slot;
     if ((rc = stage_descs(ctx, v, stream, &dd, &slot))) return rc;
-    HIP_TRY(ctx, launch_eval_large(dd, (int)v.size(), blocks, bf16, ctx->consts, stream));
+    if ((rc = emit_launch(ctx, Launch{L_LARGE, dd, (int)v.size(), 0, blocks, 0, bf16, false, 0, 0, 0}, stream)))
+        return rc;
     if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     // combine: one thread per point, blocks of 256 points
     std::vector<EvalDesc> c = v;
@@ -466,7 +488,8 @@ int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStre
         cblocks += d.nblocks;
     }
     if ((rc = stage_descs(ctx, c, stream, &dd, &slot))) return rc;
-    HIP_TRY(ctx, launch_eval_large_combine(dd, (int)c.size(), cblocks, ctx->consts, stream));
+    if ((rc = emit_launch(ctx, Launch{L_COMBINE, dd, (int)c.size(), 0, cblocks, 0, false, false, 0, 0, 0}, stream)))
+        return rc;
     if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     return SEVO_OK;
 }
@@ -476,6 +499,7 @@ int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStre
 
 int sevo::Workspace::get(sevo_ctx *ctx, int which, size_t bytes, void **out)
 {
+    if (ctx->rec) return plan_alloc(ctx, std::max<size_t>(bytes, 256), out);   // a plan's own workspace
     Buf &b = bufs[which];
     if (b.bytes < bytes) {
         if (b.ptr) {
@@ -530,7 +554,7 @@ int sevo::finish_slot(sevo_ctx *ctx, int slot, hipStream_t stream)
     return finish_slot_impl(ctx, slot, stream);
 }
 
-int sevo::fork_streams(sevo_ctx *ctx, hipStream_t parent, int n, hipStream_t *out)
+static int ensure_streams(sevo_ctx *ctx, int n)
 {
     while ((int)ctx->streams.size() < n) {
         hipStream_t s;
@@ -542,6 +566,13 @@ int sevo::fork_streams(sevo_ctx *ctx, hipStream_t parent, int n, hipStream_t *ou
         HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
         ctx->fork_ev.push_back(e);
     }
+    return SEVO_OK;
+}
+
+int sevo::fork_streams(sevo_ctx *ctx, hipStream_t parent, int n, hipStream_t *out)
+{
+    int rc = ensure_streams(ctx, n);
+    if (rc) return rc;
     HIP_TRY(ctx, hipEventRecord(ctx->fork_ev[n], parent));
     for (int k = 0; k < n; ++k) {
         HIP_TRY(ctx, hipStreamWaitEvent(ctx->streams[k], ctx->fork_ev[n], 0));
@@ -569,6 +600,73 @@ sevo::DeviceScope::~DeviceScope()
 {
     int cur = -1;
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
+
+sevo_plan *sevo::ctx_recording(sevo_ctx *ctx) { return ctx->rec; }
+
+int sevo::plan_alloc(sevo_ctx *ctx, size_t bytes, void **out)
+{
+    void *d = nullptr;
+    HIP_TRY(ctx, hipMalloc(&d, std::max<size_t>(bytes, 16)));
+    ctx->rec->dev.push_back(d);
+    *out = d;
+    return SEVO_OK;
+}
+
+static hipError_t exec_launch(sevo_ctx *ctx, const sevo::Launch &L, hipStream_t s)
+{
+    using namespace sevo;
+    switch (L.kind) {
+    case L_SMALL:
+        return launch_eval_small((const EvalDesc *)L.d, L.n, L.ks, L.total, L.grid, ctx->consts, s);
+    case L_F64: return launch_eval_f64((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
+    case L_LARGE: return launch_eval_large((const EvalDesc *)L.d, L.n, L.total, L.flag, ctx->consts, s);
+    case L_COMBINE: return launch_eval_large_combine((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
+    case L_RUN: return exec_run_launch(L, s, fold_seed(ctx->base_seed), ctx->consts);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int sevo::emit_launch(sevo_ctx *ctx, const Launch &L, hipStream_t stream)
+{
+    if (ctx->rec) {
+        ctx->rec->launches.push_back(L);
+        ctx->rec->lanes = std::max(ctx->rec->lanes, L.lane + 1);
+        return SEVO_OK;
+    }
+    HIP_TRY(ctx, exec_launch(ctx, L, stream));
+    return SEVO_OK;
+}
+
+static void free_plan(sevo_plan *p)
+{
+    if (!p) return;
+    if (!p->dev.empty()) (void)hipDeviceSynchronize();
+    for (void *d : p->dev) (void)hipFree(d);
+    delete p;
+}
+
+int sevo::plan_begin(sevo_ctx *ctx)
+{
+    if (ctx->rec) return fail(ctx, SEVO_ESTATE, "a plan is already being built on this context");
+    ctx->rec = new sevo_plan;
+    ctx->rec->ctx = ctx;
+    return SEVO_OK;
+}
+
+int sevo::plan_finish(sevo_ctx *ctx, int rc, sevo_plan **out)
+{
+    sevo_plan *p = ctx->rec;
+    ctx->rec = nullptr;
+    // create the internal streams now: launching the plan creates nothing
+    if (rc == SEVO_OK && p && p->lanes > 1) rc = ensure_streams(ctx, p->lanes);
+    if (rc != SEVO_OK) {
+        free_plan(p);
+        *out = nullptr;
+        return rc;
+    }
+    *out = p;
+    return SEVO_OK;
 }
 
 const Consts &sevo::ctx_consts(sevo_ctx *ctx) { return ctx->consts; }
@@ -812,6 +910,45 @@ int sevo_tune_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_ite
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int sevo_plan_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items, int32_t precision,
+                       sevo_plan **out)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    if (!out) return fail(ctx, SEVO_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_precision(ctx, precision);
+    if (rc) return rc;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, SEVO_EINVAL, "bad item list");
+    DeviceGuard g(ctx->device);
+    std::vector<std::pair<EvalDesc, int>> v;
+    if ((rc = build_items(ctx, items, n_items, v))) return rc;   // instances made before recording
+    if ((rc = plan_begin(ctx))) return rc;
+    rc = eval_items(ctx, v, precision, nullptr);
+    return plan_finish(ctx, rc, out);
+}
+
+int sevo_plan_launch(sevo_plan *plan, void *stream)
+{
+    if (!plan) return fail(nullptr, SEVO_EINVAL, "plan is NULL");
+    sevo_ctx *ctx = plan->ctx;
+    DeviceGuard g(ctx->device);
+    const hipStream_t s = (hipStream_t)stream;
+    std::vector<hipStream_t> ss(plan->lanes, s);
+    int rc;
+    if (plan->lanes > 1 && (rc = fork_streams(ctx, s, plan->lanes, ss.data()))) return rc;
+    for (const Launch &L : plan->launches) HIP_TRY(ctx, exec_launch(ctx, L, ss[L.lane]));
+    if (plan->lanes > 1) return join_streams(ctx, s, plan->lanes, ss.data());
+    return SEVO_OK;
+}
+
+int sevo_plan_destroy(sevo_plan *plan)
+{
+    if (!plan) return SEVO_OK;
+    DeviceGuard g(plan->ctx->device);
+    free_plan(plan);
+    return SEVO_OK;
 }
 
 int sevo_evaluate(sevo_ctx *ctx, const sevo_problem *prob, uint32_t instance, const void *x,

@@ -35,6 +35,31 @@ struct InstanceView {
 
 int set_error(sevo_ctx *ctx, int code, const char *msg);
 
+// One kernel launch of a call, kept by a plan (sevo_plan_*) to be enqueued
+// again later with nothing but launches.
+enum { L_SMALL = 0, L_F64 = 1, L_LARGE = 2, L_COMBINE = 3, L_RUN = 4 };
+struct Launch {
+    int kind;
+    const void *d;      // device descriptors
+    int n, ks, total, grid;
+    bool flag;          // L_LARGE: split bf16; L_RUN: population on chip
+    bool wave;          // L_RUN: wave teams
+    size_t shm;         // L_RUN: dynamic LDS bytes
+    int stride;         // L_RUN: floats of dynamic LDS per run
+    int lane;           // internal stream of the launch (runs: one per group)
+};
+// While a plan is being built the context records launches instead of
+// enqueueing them, and descriptor tables and workspace come from
+// plan-owned device memory (ctx_recording() != nullptr).
+sevo_plan *ctx_recording(sevo_ctx *ctx);
+int emit_launch(sevo_ctx *ctx, const Launch &L, hipStream_t stream);
+int plan_alloc(sevo_ctx *ctx, size_t bytes, void **out);
+hipError_t exec_run_launch(const Launch &L, hipStream_t stream, uint32_t seed32, const Consts &k);
+// Start recording a plan on the context; plan_finish stops, and on success
+// (rc == 0) hands the plan out, else frees it and returns rc.
+int plan_begin(sevo_ctx *ctx);
+int plan_finish(sevo_ctx *ctx, int rc, sevo_plan **out);
+
 // Makes the context's GPU current for the scope of a call.
 struct DeviceScope {
     int prev = -1;

@@ -112,6 +112,10 @@ def lib():
     L.sevo_pso_step.argtypes = [vp, C.POINTER(Problem), u32, C.POINTER(PSOState),
                                 C.POINTER(PSOParams), i32, vp]
     L.sevo_run.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, vp]
+    L.sevo_plan_evaluate.argtypes = [vp, C.POINTER(EvalItem), i32, i32, C.POINTER(vp)]
+    L.sevo_plan_run.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, C.POINTER(vp)]
+    L.sevo_plan_launch.argtypes = [vp, vp]
+    L.sevo_plan_destroy.argtypes = [vp]
     for f in header_functions():
         if f != "sevo_last_error":
             getattr(L, f).restype = C.c_int
@@ -149,6 +153,29 @@ def generate_instance(func, dim, inst, instance_seed=250517431):
 
 def problem(func, dim, lb=-100.0, ub=100.0, f_star=100.0):
     return Problem(func, dim, lb, ub, f_star)
+
+
+class Plan:
+    """A prepared evaluation or set of runs (sevo_plan_*): launch() enqueues
+    kernels only, so it can be captured into a graph and replayed."""
+
+    def __init__(self, ctx, handle):
+        self._ctx = ctx
+        self._h = handle
+
+    def launch(self, stream=None):
+        self._ctx._check(self._ctx._L.sevo_plan_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._ctx._L.sevo_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -234,6 +261,19 @@ class Context:
         chosen = (C.c_int32 * 64)()
         self._check(self._L.sevo_tune_evaluate(self._h, arr, len(arr), precision, _stream(stream), chosen))
         return {k: chosen[k] for k in range(64) if chosen[k] >= 0}
+
+    def plan_evaluate(self, items, precision=FP32):
+        arr = items if isinstance(items, C.Array) else self.prepare_batch(items)
+        h = C.c_void_p()
+        self._check(self._L.sevo_plan_evaluate(self._h, arr, len(arr), precision, C.byref(h)))
+        return Plan(self, h)
+
+    def plan_run(self, descs, results, trace=None, trace_len=0, best_x=None, max_dim=0, precision=FP32):
+        arr = (RunDesc * len(descs))(*descs)
+        h = C.c_void_p()
+        self._check(self._L.sevo_plan_run(self._h, arr, len(descs), precision, _ptr(results), _ptr(trace),
+                                          trace_len, _ptr(best_x), max_dim, C.byref(h)))
+        return Plan(self, h)
 
     def de_step(self, prob, inst, state: DEState, F, CR, precision=FP32, stream=None):
         self._check(self._L.sevo_de_step(self._h, C.byref(prob), inst, C.byref(state),
