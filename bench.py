@@ -260,18 +260,30 @@ def _run_descs(S, specs):
     return out
 
 
-def _time_runs(ctx, S, torch, descs, precision, steps, warmup, trace_len=0):
+def _time_runs(ctx, S, torch, descs, precision, steps, warmup, trace_len=0, graph=False):
+    """Mean ms per call of the runs.  graph: the FP32 runs as a plan whose
+    launch is captured into a HIP graph once and replayed (persistent fused
+    kernels + graph); otherwise one sevo_run call per step."""
     n = len(descs)
     res = torch.zeros((n, 32), dtype=torch.uint8, device="cuda")
     tr = torch.zeros(max(1, n * trace_len), device="cuda") if trace_len else None
     st = torch.cuda.current_stream()
+    if graph:
+        plan = ctx.plan_run(descs, res, tr, trace_len, precision=precision)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.launch(torch.cuda.current_stream())
+        call = g.replay
+    else:
+        def call():
+            ctx.run(descs, res, tr, trace_len, precision=precision, stream=st)
     for _ in range(warmup):
-        ctx.run(descs, res, tr, trace_len, precision=precision, stream=st)
+        call()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(steps):
-        ctx.run(descs, res, tr, trace_len, precision=precision, stream=st)
+        call()
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -327,10 +339,10 @@ def run_workload(a):
         spec = [(S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001, 0, 0)]
         descs = _run_descs(S, spec)
         ms64, r64 = _time_runs(ctx, S, torch, descs, S.FP64, steps, warm, trace_len=250)
-        ms32, r32 = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm, trace_len=250)
+        ms32, r32 = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm, trace_len=250, graph=True)
         ev = r64[0].fes
         extra = {"fused_fp32": {"evals_per_s": ev / (ms32 / 1e3), "ms": ms32,
-                                "best_e": r32[0].best_e},
+                                "best_e": r32[0].best_e, "launch": "HIP graph replay of a plan"},
                  "plain_fp64": {"evals_per_s": ev / (ms64 / 1e3), "ms": ms64, "best_e": r64[0].best_e},
                  "speedup_fused_vs_plain": ms64 / ms32}
         if not a.no_cpu:
@@ -344,7 +356,7 @@ def run_workload(a):
             f, d, k = W.c3_swarm(sw)
             spec.append((S.ALGO_PSO, f, d, 40, 40 * 2001, k, sw))
         descs = _run_descs(S, spec)
-        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm)
+        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm, graph=True)
         ev = sum(r.fes for r in rr)
         # one swarm per launch: a sample of 24 swarms (8 per dimension), each its own call
         sample = [descs[i] for i in range(0, 4096, 4096 // 24)][:24]
@@ -367,7 +379,8 @@ def run_workload(a):
             extra["cpu_baseline"] = _oracle_runs(spec[::64], 10)
         _line(metric, ev / (ms / 1e3), "evals/s", steps, warm, ms,
               {"workload": "batched PSO: 4096 swarms x 40 particles, D in {10,30,50} x 6 functions x "
-                           "10 instances, 2000 iterations, one fused launch per dimension class",
+                           "10 instances, 2000 iterations, persistent fused kernels (one launch per "
+                           "dimension class) replayed from a HIP graph",
                "evals": ev}, **extra)
     elif a.workload == "c4":
         spec = []
@@ -375,16 +388,18 @@ def run_workload(a):
             f, d, k, np_ = W.c4_run(r)
             spec.append((S.ALGO_SHADE, f, d, np_, 10000 * d, k, r))
         descs = _run_descs(S, spec)
-        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, 1, 0)
+        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, 1, 0, graph=True)
         ev = sum(r.fes for r in rr)
         succ = sum(r.success for r in rr)
         extra = {"successes": succ}
         if not a.no_cpu:
-            small = [sp for sp in spec if sp[2] == 10][:64]
-            extra["cpu_baseline"] = _oracle_runs(small, 10)
+            # 16 runs, 4 per dimension (run r has D = (10, 30, 50, 100)[r mod 4]; a
+            # stride of 129 runs steps through the four)
+            extra["cpu_baseline"] = _oracle_runs([spec[(k * 129) % 2048] for k in range(16)], 10)
         _line(metric, ev / (ms / 1e3), "evals/s", 1, 0, ms,
               {"workload": "batched SHADE: 2048 runs, D in {10,30,50,100}, NP = min(18 D, 200), "
-                           "budget 10000 D, p = 0.1, H = 6", "evals": ev}, **extra)
+                           "budget 10000 D, p = 0.1, H = 6, persistent fused kernels replayed from a "
+                           "HIP graph", "evals": ev}, **extra)
     elif a.workload == "c5":
         out = {}
         for prec, name in ((S.SPLIT_BF16, "split_bf16"), (S.FP32, "fp32")):

@@ -10,21 +10,28 @@
 """
 import itertools
 
+import os
+
 import numpy as np
 import pytest
 from scipy import stats
 
 import oracle as O
 
-# (counter, key, expected output) -- Random123 known-answer vectors for philox4x32 R=10.
-KAT = [
-    ([0x00000000, 0x00000000, 0x00000000, 0x00000000], [0x00000000, 0x00000000],
-     [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
-    ([0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff], [0xffffffff, 0xffffffff],
-     [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
-    ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
-     [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]),
-]
+def _load_kat():
+    """(counter, key, expected output) rows of tests/golden/philox4x32_10_kat.txt."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(t, 16) for t in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+KAT = _load_kat()
 
 
 @pytest.mark.parametrize("ctr,key,want", KAT)
