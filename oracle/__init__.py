@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
-ALGO_DE, ALGO_PSO, ALGO_SHADE = 0, 1, 2
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE = 0, 1, 2, 3
 TRACE_EVERY = 200
 
 
@@ -52,7 +52,14 @@ class RunDesc(C.Structure):
         ("F", C.c_double), ("CR", C.c_double),
         ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
         ("p", C.c_double), ("H", C.c_int32),
+        ("r_arc", C.c_double), ("np_min", C.c_int32),
     ]
+
+
+class _LShadeState(C.Structure):
+    _fields_ = [("np", C.c_int32), ("na", C.c_int32), ("acap", C.c_int32), ("H", C.c_int32),
+                ("pos", C.c_int32), ("X", C.POINTER(C.c_double)), ("eX", C.POINTER(C.c_double)),
+                ("A", C.POINTER(C.c_double)), ("MF", C.c_double * 64), ("MCR", C.c_double * 64)]
 
 
 class RunResult(C.Structure):
@@ -109,6 +116,13 @@ def lib():
         L.orc_shade_memory_update.argtypes = [C.c_int32, dp, dp, ip, C.c_int32, dp, dp, dp]
         L.orc_shade_pnum.restype = C.c_int32
         L.orc_shade_pnum.argtypes = [C.c_double, C.c_int32]
+        L.orc_lshade_np.restype = C.c_int32
+        L.orc_lshade_np.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int64]
+        L.orc_lshade_archive_max.restype = C.c_int32
+        L.orc_lshade_archive_max.argtypes = [C.c_double, C.c_int32]
+        L.orc_lshade_memory_update.argtypes = [C.c_int32, dp, dp, ip, C.c_int32, dp, dp, dp]
+        L.orc_lshade_generation.argtypes = [pp, dp, dp, C.POINTER(_LShadeState), C.c_double, C.c_double,
+                                            C.c_int32, C.c_uint32, C.c_uint64, C.c_uint32, dp, dp, ip]
         L.orc_run.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
                               dp, C.c_int64, dp]
         for name in ("orc_schwefel_s", "orc_schwefel_c", "orc_schwefel_lambda"):
@@ -325,6 +339,69 @@ def shade_memory_update(MF, MCR, pos, SF, SCR, dS):
     lib().orc_shade_memory_update(MF.shape[0], _d(MF), _d(MCR), _p(posa, C.c_int32),
                                   SF.shape[0], _d(SF), _d(SCR), _d(dS))
     return MF, MCR, int(posa[0])
+
+
+def lshade_np(np_init, np_min, budget, fe):
+    return int(lib().orc_lshade_np(np_init, np_min, C.c_int64(budget), C.c_int64(fe)))
+
+
+def lshade_archive_max(r_arc, np_):
+    return int(lib().orc_lshade_archive_max(C.c_double(r_arc), np_))
+
+
+def lshade_memory_update(MF, MCR, pos, SF, SCR, dS):
+    MF = np.ascontiguousarray(MF, dtype=np.float64).copy()
+    MCR = np.ascontiguousarray(MCR, dtype=np.float64).copy()
+    SF, SCR, dS = (np.ascontiguousarray(a, dtype=np.float64) for a in (SF, SCR, dS))
+    posa = np.array([pos], dtype=np.int32)
+    lib().orc_lshade_memory_update(MF.shape[0], _d(MF), _d(MCR), _p(posa, C.c_int32),
+                                   SF.shape[0], _d(SF), _d(SCR), _d(dS))
+    return MF, MCR, int(posa[0])
+
+
+class LShade:
+    """One L-SHADE run's state in the oracle, advanced a generation at a time."""
+
+    def __init__(self, func, dim, lb, ub, o, M, X, eX, H=6, r_arc=2.6):
+        self.pb = _Problem(func, dim, lb, ub)
+        self.o = np.ascontiguousarray(o, dtype=np.float64)
+        self.M = np.ascontiguousarray(M, dtype=np.float64)
+        np_ = X.shape[0]
+        self.X = np.ascontiguousarray(X, dtype=np.float64).copy()
+        self.eX = np.ascontiguousarray(eX, dtype=np.float64).copy()
+        self.acap = lshade_archive_max(r_arc, np_) + 1
+        self.A = np.zeros((self.acap, dim))
+        self.r_arc = r_arc
+        self.st = _LShadeState(np_, 0, self.acap, H, 0, _d(self.X), _d(self.eX), _d(self.A))
+        for k in range(H):
+            self.st.MF[k] = 0.5
+            self.st.MCR[k] = 0.5
+
+    @property
+    def np(self):
+        return self.st.np
+
+    @property
+    def na(self):
+        return self.st.na
+
+    def memory(self):
+        H = self.st.H
+        return np.array(self.st.MF[:H]), np.array(self.st.MCR[:H]), self.st.pos
+
+    def generation(self, p, np_next, run_uid, seed, t):
+        """Returns (trials U, their errors eU, number of successes)."""
+        n = self.st.np
+        D = self.pb.dim
+        U = np.zeros((n, D))
+        eU = np.zeros(n)
+        ns = np.zeros(1, dtype=np.int32)
+        rc = lib().orc_lshade_generation(C.byref(self.pb), _d(self.o), _d(self.M), C.byref(self.st),
+                                        C.c_double(p), C.c_double(self.r_arc), np_next, run_uid,
+                                        C.c_uint64(seed), t, _d(U), _d(eU), _p(ns, C.c_int32))
+        if rc != 0:
+            raise ValueError("orc_lshade_generation failed")
+        return U, eU, int(ns[0])
 
 
 def run(desc: dict, seed, inst_seed, trace_len=0):

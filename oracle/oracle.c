@@ -650,6 +650,171 @@ int orc_shade_generation(const orc_problem *pb, const double *o, const double *M
 }
 
 /* ------------------------------------------------------------------------- */
+/* L-SHADE (Tanabe & Fukunaga, CEC 2014). */
+
+int32_t orc_lshade_np(int32_t np_init, int32_t np_min, int64_t budget, int64_t fe)
+{
+    double v = (double)(np_min - np_init) * (double)fe / (double)budget + (double)np_init;
+    long k = lround(v);
+    if (k < np_min) k = np_min;
+    if (k > np_init) k = np_init;
+    return (int32_t)k;
+}
+
+int32_t orc_lshade_archive_max(double r_arc, int32_t np)
+{
+    long k = lround(r_arc * (double)np);
+    return k < 0 ? 0 : (int32_t)k;
+}
+
+void orc_lshade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos, int32_t n_s,
+                              const double *SF, const double *SCR, const double *dS)
+{
+    if (n_s <= 0) return;
+    double total = 0.0, cr_max = 0.0;
+    for (int k = 0; k < n_s; ++k) {
+        total += dS[k];
+        if (SCR[k] > cr_max) cr_max = SCR[k];
+    }
+    double nf = 0.0, df = 0.0, nc = 0.0, dc = 0.0;
+    for (int k = 0; k < n_s; ++k) {
+        double wk = dS[k] / total;
+        nf += wk * SF[k] * SF[k];
+        df += wk * SF[k];
+        nc += wk * SCR[k] * SCR[k];
+        dc += wk * SCR[k];
+    }
+    /* the terminal CR value is kept once reached, or set when every
+       successful CR was zero */
+    if (MCR[*pos] < 0.0 || cr_max == 0.0) MCR[*pos] = -1.0;
+    else MCR[*pos] = nc / dc;
+    MF[*pos] = nf / df;
+    *pos = (*pos + 1) % H;
+}
+
+int orc_lshade_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
+                          double p, double r_arc, int32_t np_next, uint32_t run_uid, uint64_t seed,
+                          uint32_t t, double *U, double *eU, int32_t *n_success)
+{
+    const int D = pb->dim, np = s->np;
+    if (np < 4 || D < 1 || s->H < 1 || np_next < 4 || np_next > np) return -1;
+    const size_t uD = (size_t)D;
+    int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
+    double *v = (double *)malloc(sizeof(double) * uD);
+    double *Fi = (double *)malloc(sizeof(double) * (size_t)np * 5);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)np * (uD + 1));
+    if (!rank || !v || !Fi || !tmp) { free(rank); free(v); free(Fi); free(tmp); return -1; }
+    double *CRi = Fi + np, *SF = Fi + 2 * (size_t)np, *SCR = Fi + 3 * (size_t)np, *dS = Fi + 4 * (size_t)np;
+    for (int i = 0; i < np; ++i) rank[i] = i;
+    g_sort_keys = s->eX;
+    qsort(rank, (size_t)np, sizeof(int32_t), cmp_rank);
+    const int32_t pnum = orc_shade_pnum(p, np);
+    const int32_t H = s->H;
+
+    /* variation */
+    for (int i = 0; i < np; ++i) {
+        uint32_t wp[4], wc[4], wd[4];
+        draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_SHADE_P, 0, 0, wp);
+        const int32_t k = (int32_t)orc_range(wp[0], (uint32_t)H);
+        double cr = 0.0;
+        if (s->MCR[k] >= 0.0) {
+            double nrm = sqrt(-2.0 * log(1.0 - orc_u24(wp[1]))) * cos(2.0 * M_PI * orc_u24(wp[2]));
+            cr = s->MCR[k] + 0.1 * nrm;
+            if (cr < 0.0) cr = 0.0;
+            if (cr > 1.0) cr = 1.0;
+        }
+        int retries = 0;
+        double F = -1.0, cm = INFINITY;
+        while (retries < SHADE_MAX_RETRIES) {
+            draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_SHADE_C, 0, (uint32_t)retries, wc);
+            double Fc = s->MF[k] + 0.1 * tan(M_PI * (orc_u24(wc[0]) - 0.5));
+            if (Fc > 0.0) { F = Fc; break; }
+            ++retries;
+        }
+        if (!(F > 0.0)) F = s->MF[k];
+        if (F > 1.0) F = 1.0;
+        const int32_t pbi = rank[orc_range(wp[3], (uint32_t)pnum)];
+        draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_SHADE_D, 0, 0, wd);
+        int32_t ex[2] = { i, 0 };
+        const int32_t r1 = draw_excluding(wd[0], np, ex, 1);
+        ex[1] = r1;
+        const int32_t r2 = draw_excluding(wd[1], np + s->na, ex, 2);   /* >= np: archive */
+        const int32_t jrand = (int32_t)orc_range(wd[2], (uint32_t)D);
+        const double *xi = s->X + (size_t)i * uD, *xp = s->X + (size_t)pbi * uD;
+        const double *x1 = s->X + (size_t)r1 * uD;
+        const double *x2 = r2 < np ? s->X + (size_t)r2 * uD : s->A + (size_t)(r2 - np) * uD;
+        for (int j = 0; j < D; ++j) v[j] = xi[j] + F * (xp[j] - xi[j]) + F * (x1[j] - x2[j]);
+        crossover_repair(pb, i, run_uid, seed, t, orc_cr_threshold(cr), jrand, v, xi, U + (size_t)i * uD, NULL,
+                         &cm);
+        Fi[i] = F;
+        CRi[i] = cr;
+    }
+    orc_error_aos(pb->func, D, o, M, U, np, eU);
+
+    /* selection; improved parents enter the archive in index order */
+    const int32_t amax = orc_lshade_archive_max(r_arc, np);
+    int32_t n_s = 0;
+    for (int i = 0; i < np; ++i) {
+        const double ku = key_of(eU[i]), kx = key_of(s->eX[i]);
+        if (ku < kx) {
+            double d = kx - ku;
+            if (!(d <= SHADE_DELTA_CAP)) d = SHADE_DELTA_CAP;
+            SF[n_s] = Fi[i]; SCR[n_s] = CRi[i]; dS[n_s] = d; ++n_s;
+            int32_t at = -1;
+            if (s->na < amax) {
+                at = s->na++;
+            } else if (amax > 0) {
+                uint32_t wa[4];
+                draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_LSHADE_A, 0, 0, wa);
+                at = (int32_t)orc_range(wa[0], (uint32_t)amax);
+            }
+            if (at >= 0) memcpy(s->A + (size_t)at * uD, s->X + (size_t)i * uD, sizeof(double) * uD);
+        }
+        if (ku <= kx) {
+            memcpy(s->X + (size_t)i * uD, U + (size_t)i * uD, sizeof(double) * uD);
+            s->eX[i] = eU[i];
+        }
+    }
+    orc_lshade_memory_update(H, s->MF, s->MCR, &s->pos, n_s, SF, SCR, dS);
+    if (n_success) *n_success = n_s;
+
+    /* population size reduction: keep the best np_next, in index order */
+    if (np_next < np) {
+        for (int i = 0; i < np; ++i) rank[i] = i;
+        g_sort_keys = s->eX;
+        qsort(rank, (size_t)np, sizeof(int32_t), cmp_rank);
+        uint8_t *keep = (uint8_t *)calloc((size_t)np, 1);
+        if (!keep) { free(rank); free(v); free(Fi); free(tmp); return -1; }
+        for (int r = 0; r < np_next; ++r) keep[rank[r]] = 1;
+        int32_t m = 0;
+        for (int i = 0; i < np; ++i) {
+            if (!keep[i]) continue;
+            memcpy(tmp + (size_t)m * uD, s->X + (size_t)i * uD, sizeof(double) * uD);
+            tmp[(size_t)np * uD + m] = s->eX[i];
+            ++m;
+        }
+        for (int i = 0; i < np_next; ++i) {
+            memcpy(s->X + (size_t)i * uD, tmp + (size_t)i * uD, sizeof(double) * uD);
+            s->eX[i] = tmp[(size_t)np * uD + i];
+        }
+        free(keep);
+        s->np = np_next;
+        /* archive cut to its new bound by random removals */
+        const int32_t amax2 = orc_lshade_archive_max(r_arc, np_next);
+        for (uint32_t k = 0; s->na > amax2; ++k) {
+            uint32_t wr[4];
+            draw(run_uid, seed, t, k, ORC_TAG_LSHADE_S, 0, 0, wr);
+            const int32_t at = (int32_t)orc_range(wr[0], (uint32_t)s->na);
+            if (at != s->na - 1)
+                memcpy(s->A + (size_t)at * uD, s->A + (size_t)(s->na - 1) * uD, sizeof(double) * uD);
+            --s->na;
+        }
+    }
+    free(rank); free(v); free(Fi); free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Run driver. */
 
 typedef struct {
@@ -682,7 +847,7 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
 {
     int D = d->dim, np = d->np;
     if (D < 1 || np < 1) return -1;
-    if ((d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE) && np < 4) return -1;
+    if ((d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE || d->algo == ORC_ALGO_LSHADE) && np < 4) return -1;
     orc_problem pb = { d->func, D, d->lb, d->ub };
     size_t pop = (size_t)np * D;
     double *o = (double *)malloc(sizeof(double) * (size_t)D);
@@ -735,6 +900,33 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             memcpy(X, Xn, sizeof(double) * pop);
             memcpy(eX, eXn, sizeof(double) * (size_t)np);
         }
+    } else if (d->algo == ORC_ALGO_LSHADE) {
+        const int32_t np_min = d->np_min;
+        if (np_min < 4 || np_min > np) { free(o); free(M); free(buf); return -1; }
+        orc_lshade_state st;
+        memset(&st, 0, sizeof(st));
+        st.np = np;
+        st.H = d->H > 0 ? (d->H > 64 ? 64 : d->H) : 1;
+        st.acap = orc_lshade_archive_max(d->r_arc, np) + 1;
+        st.X = X;
+        st.eX = eX;
+        st.A = (double *)malloc(sizeof(double) * (size_t)st.acap * D);
+        if (!st.A) { free(o); free(M); free(buf); return -1; }
+        for (int k = 0; k < st.H; ++k) { st.MF[k] = 0.5; st.MCR[k] = 0.5; }
+        double *U = A, *eU = eA;
+        orc_init_population(&pb, np, d->run_uid, seed, X);
+        orc_error_aos(d->func, D, o, M, X, np, eX);
+        for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+        while (rec.fe < d->budget) {
+            ++gens;
+            const int32_t np_old = st.np;
+            const int32_t np_next = orc_lshade_np(np, np_min, d->budget, rec.fe + np_old);
+            rc = orc_lshade_generation(&pb, o, M, &st, d->p, d->r_arc, np_next < np_old ? np_next : np_old,
+                                       d->run_uid, seed, (uint32_t)gens, U, eU, NULL);
+            if (rc != 0) break;
+            for (int i = 0; i < np_old; ++i) record(&rec, eU[i], U + (size_t)i * D);
+        }
+        free(st.A);
     } else {
         rc = -1;
     }

@@ -31,12 +31,13 @@ extern "C" {
 /* Function identifiers (same numbering as the product ABI, by definition). */
 enum { ORC_ELLIPSOID = 0, ORC_ROSENBROCK = 1, ORC_RASTRIGIN = 2,
        ORC_SCHWEFEL = 3, ORC_GRIEWANK = 4, ORC_ACKLEY = 5, ORC_NFUNC = 6 };
-enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2 };
+enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3 };
 
 /* Philox stream tags (third counter word, bits 24..31). */
 enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
        ORC_TAG_PSO_R = 4, ORC_TAG_SHADE_P = 5, ORC_TAG_SHADE_C = 6,
-       ORC_TAG_SHADE_D = 7, ORC_TAG_SHIFT_O = 16, ORC_TAG_ROT_N = 17 };
+       ORC_TAG_SHADE_D = 7, ORC_TAG_LSHADE_A = 8, ORC_TAG_LSHADE_S = 9,
+       ORC_TAG_SHIFT_O = 16, ORC_TAG_ROT_N = 17 };
 
 typedef struct {
     int32_t func;
@@ -125,6 +126,44 @@ void orc_shade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos,
                              const double *dS);
 int32_t orc_shade_pnum(double p, int32_t np);
 
+/* ---- L-SHADE (Tanabe & Fukunaga, CEC 2014): SHADE with an external
+ * archive of replaced parents, linear population size reduction and the
+ * weighted Lehmer mean for both memories (a terminal CR memory, stored as a
+ * negative value, gives CR = 0) ----
+ *
+ * State of one run.  X / eX hold the current np individuals (individual-
+ * major, rows beyond np unused); A the na archived parents (capacity acap).
+ * One generation: ranking by (error, index); per individual the SHADE draws
+ * (memory slot, CR, F with Cauchy retries, pbest among the top
+ * max(2, round(p np)), r1 in P \ {i}, r2 in P u A \ {i, r1} -- values at or
+ * above np index the archive -- and jrand); current-to-pbest/1, binomial
+ * crossover, midpoint repair; evaluation; selection (e(u) <= e(x)); every
+ * strictly improved parent enters the archive, in index order: appended
+ * while the archive holds fewer than round(r_arc np) members, else written
+ * over the member at range(w, that bound), w from tag LSHADE_A; memory
+ * update; then reduction to np_next individuals (the best by (error,
+ * index), kept in index order) and the archive cut to round(r_arc np_next)
+ * by removing random members (k-th removal: position range(w, na) with w
+ * from tag LSHADE_S and counter (t, k), the last member moved into it).
+ * U / eU receive the np trials and their errors. */
+typedef struct {
+    int32_t np, na, acap, H, pos;
+    double *X, *eX, *A;
+    double MF[64], MCR[64];
+} orc_lshade_state;
+
+/* Population size after `fe` of `budget` evaluations:
+ * round((np_min - np_init) fe / budget + np_init), within [np_min, np_init]. */
+int32_t orc_lshade_np(int32_t np_init, int32_t np_min, int64_t budget, int64_t fe);
+/* Archive bound round(r_arc np). */
+int32_t orc_lshade_archive_max(double r_arc, int32_t np);
+int orc_lshade_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
+                          double p, double r_arc, int32_t np_next, uint32_t run_uid, uint64_t seed,
+                          uint32_t t, double *U, double *eU, int32_t *n_success);
+/* Memory update of L-SHADE from the successful set. */
+void orc_lshade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos, int32_t n_s,
+                              const double *SF, const double *SCR, const double *dS);
+
 /* ---- Whole-run driver with FE accounting and the 200-FE recorder ---- */
 typedef struct {
     int32_t algo;
@@ -136,8 +175,10 @@ typedef struct {
     int64_t budget;        /* function evaluations */
     double F, CR;          /* DE */
     double w, c1, c2, vmax;/* PSO */
-    double p;              /* SHADE: pbest fraction */
-    int32_t H;             /* SHADE: memory size */
+    double p;              /* SHADE / L-SHADE: pbest fraction */
+    int32_t H;             /* SHADE / L-SHADE: memory size */
+    double r_arc;          /* L-SHADE: archive bound per individual */
+    int32_t np_min;        /* L-SHADE: final population size */
 } orc_run_desc;
 
 typedef struct {

@@ -312,3 +312,102 @@ def test_run_c1_de_converges():
     assert res["generations"] == 1000 and res["fes"] == 50050
     assert res["best_e"] < trace[0]
     assert res["success"] == (res["best_e"] <= 1e-8)
+
+
+# ------------------------------------------------------------------ L-SHADE
+
+def test_lshade_population_schedule():
+    """Linear reduction: NP_init at the start, NP_min at the budget, never
+    increasing, one step per (NP_init - NP_min)^-1 of the budget."""
+    n0, nmin, B = 180, 4, 100000
+    assert O.lshade_np(n0, nmin, B, 0) == n0
+    assert O.lshade_np(n0, nmin, B, B) == nmin
+    assert O.lshade_np(n0, nmin, B, 2 * B) == nmin            # clamped past the budget
+    seq = [O.lshade_np(n0, nmin, B, fe) for fe in range(0, B + 1, 97)]
+    assert all(a >= b for a, b in zip(seq, seq[1:]))
+    assert O.lshade_np(n0, nmin, B, B // 2) in (92, 93)        # halfway: (180 + 4) / 2
+    assert O.lshade_archive_max(2.6, 180) == 468 and O.lshade_archive_max(0.0, 50) == 0
+
+
+def test_lshade_memory_update_closed_form():
+    """Weighted Lehmer means for F and CR; the terminal CR value (stored as
+    -1) is set when every successful CR is 0 and then kept."""
+    MF, MCR = np.full(3, 0.5), np.full(3, 0.5)
+    # one success: both means are its own values
+    MF, MCR, pos = O.lshade_memory_update(MF, MCR, 0, [0.7], [0.3], [2.0])
+    assert (MF[0], MCR[0], pos) == (pytest.approx(0.7), pytest.approx(0.3), 1)
+    # two successes, weights 1/4 and 3/4: mean_L = (w1 a^2 + w2 b^2) / (w1 a + w2 b)
+    MF, MCR, pos = O.lshade_memory_update(MF, MCR, pos, [0.2, 0.6], [0.4, 0.8], [1.0, 3.0])
+    assert MF[1] == pytest.approx((0.25 * 0.04 + 0.75 * 0.36) / (0.25 * 0.2 + 0.75 * 0.6))
+    assert MCR[1] == pytest.approx((0.25 * 0.16 + 0.75 * 0.64) / (0.25 * 0.4 + 0.75 * 0.8))
+    assert pos == 2
+    # all successful CR zero: terminal; it stays terminal in that slot
+    MF, MCR, pos = O.lshade_memory_update(MF, MCR, pos, [0.5], [0.0], [1.0])
+    assert MCR[2] == -1.0 and pos == 0
+    MF, MCR, pos = O.lshade_memory_update(MF, MCR, 2, [0.5], [0.9], [1.0])
+    assert MCR[2] == -1.0
+    # no success: nothing moves
+    MF2, MCR2, pos2 = O.lshade_memory_update(MF, MCR, pos, [], [], [])
+    assert np.array_equal(MF2, MF) and np.array_equal(MCR2, MCR) and pos2 == pos
+
+
+def test_lshade_first_generation_is_shades():
+    """With an empty archive and the initial memory, the first generation's
+    trials are SHADE's (same draws, r2 from the population only)."""
+    func, D, np_ = O.RASTRIGIN, 10, 60
+    o, M, X, eX = _pop(func, D, np_)
+    ref = O.shade_generation(func, LB, UB, o, M, X, eX, np.full(6, 0.5), np.full(6, 0.5), 0, 0.11, 9,
+                             SEED, 1)
+    ls = O.LShade(func, D, LB, UB, o, M, X, eX, H=6, r_arc=2.6)
+    U, eU, ns = ls.generation(0.11, np_, 9, SEED, 1)
+    assert np.array_equal(U, ref["U"]) and np.array_equal(eU, ref["eU"])
+    assert ns == int(np.sum(ref["eU"] < eX))
+    assert ls.na == ns                                   # every improved parent archived
+
+
+def test_lshade_generation_invariants():
+    """Over many generations with reduction: the archive never exceeds
+    round(r_arc NP) and holds only former population members; the kept
+    individuals are the best of the selected population, in index order;
+    per-slot errors never rise before the reduction."""
+    func, D, n0, r_arc = O.ROSENBROCK, 8, 40, 1.4
+    o, M, X, eX = _pop(func, D, n0)
+    ls = O.LShade(func, D, LB, UB, o, M, X, eX, H=6, r_arc=r_arc)
+    seen = {tuple(x) for x in X}
+    B = 40 * 60
+    fe = n0
+    for t in range(1, 60):
+        n = ls.np
+        if fe >= B:
+            break
+        nn = O.lshade_np(n0, 4, B, fe + n)
+        before_X, before_e = ls.X[:n].copy(), ls.eX[:n].copy()
+        U, eU, ns = ls.generation(0.11, min(nn, n), 9, SEED, t)
+        fe += n
+        seen |= {tuple(x) for x in U}
+        assert ns == int(np.sum(eU < before_e))
+        # selection result before the reduction, reconstructed from the trials
+        sel = np.where((eU <= before_e)[:, None], U, before_X)
+        sel_e = np.where(eU <= before_e, eU, before_e)
+        k = ls.np
+        keep = np.sort(np.lexsort((np.arange(n), sel_e))[:k])
+        assert np.array_equal(ls.X[:k], sel[keep]) and np.array_equal(ls.eX[:k], sel_e[keep])
+        assert ls.na <= O.lshade_archive_max(r_arc, ls.np)
+        for a in ls.A[:ls.na]:
+            assert tuple(a) in seen
+    assert ls.np < n0
+
+
+def test_lshade_run_fe_accounting():
+    d = _desc(O.ALGO_LSHADE, O.SCHWEFEL, 10, 180, 20000, p=0.11, r_arc=2.6, np_min=4)
+    res, trace, _ = O.run(d, SEED, ISEED, trace_len=100)
+    # replay the population schedule: whole generations, NP from the formula
+    fe, n, gens = 180, 180, 0
+    while fe < d["budget"]:
+        nn = min(O.lshade_np(180, 4, d["budget"], fe + n), n)
+        fe += n
+        n = nn
+        gens += 1
+    assert res["fes"] == fe and res["generations"] == gens
+    assert np.all(np.diff(trace[: fe // 200]) <= 0)
+    assert res["best_e"] <= trace[0]
