@@ -75,9 +75,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "copy"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "lshade", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
-                         "c4: batched SHADE; c5: D=1000 evaluation; copy: 512 MiB device copy "
+                         "c4: batched SHADE; c5: D=1000 evaluation; lshade: the c4 runs as L-SHADE; "
+                         "copy: 512 MiB device copy "
                          "(calibrates the HBM byte counters)")
     return ap.parse_args()
 
@@ -252,11 +253,13 @@ def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
 
 
 def _run_descs(S, specs):
-    """specs: list of (algo, func, dim, np, budget, instance, uid)."""
+    """specs: list of (algo, func, dim, np, budget, instance, uid).  L-SHADE
+    takes its published settings: p = 0.11, archive 2.6 NP, final NP 4."""
     out = []
     for (algo, func, dim, np_, budget, inst, uid) in specs:
+        p = 0.11 if algo == S.ALGO_LSHADE else 0.1
         out.append(S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, 0.7298,
-                             1.49618, 1.49618, 0.2 * (W.UB - W.LB), 0.1, 6))
+                             1.49618, 1.49618, 0.2 * (W.UB - W.LB), p, 6, 2.6, 4))
     return out
 
 
@@ -302,7 +305,8 @@ def _oracle_runs(specs, seconds):
     def one(sp):
         d = dict(zip(keys, sp))
         d.update(lb=W.LB, ub=W.UB, F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618,
-                 vmax=0.2 * (W.UB - W.LB), p=0.1, H=6)
+                 vmax=0.2 * (W.UB - W.LB), p=0.11 if d["algo"] == O.ALGO_LSHADE else 0.1, H=6,
+                 r_arc=2.6, np_min=4)
         return O.run(d, W.BASE_SEED, W.INSTANCE_SEED)[0]["fes"]
 
     t0 = time.perf_counter()
@@ -382,11 +386,12 @@ def run_workload(a):
                            "10 instances, 2000 iterations, persistent fused kernels (one launch per "
                            "dimension class) replayed from a HIP graph",
                "evals": ev}, **extra)
-    elif a.workload == "c4":
+    elif a.workload in ("c4", "lshade"):
+        algo = S.ALGO_SHADE if a.workload == "c4" else S.ALGO_LSHADE
         spec = []
         for r in range(2048):
             f, d, k, np_ = W.c4_run(r)
-            spec.append((S.ALGO_SHADE, f, d, np_, 10000 * d, k, r))
+            spec.append((algo, f, d, np_, 10000 * d, k, r))
         descs = _run_descs(S, spec)
         ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, 1, 0, graph=True)
         ev = sum(r.fes for r in rr)
@@ -397,9 +402,11 @@ def run_workload(a):
             # stride of 129 runs steps through the four)
             extra["cpu_baseline"] = _oracle_runs([spec[(k * 129) % 2048] for k in range(16)], 10)
         _line(metric, ev / (ms / 1e3), "evals/s", 1, 0, ms,
-              {"workload": "batched SHADE: 2048 runs, D in {10,30,50,100}, NP = min(18 D, 200), "
-                           "budget 10000 D, p = 0.1, H = 6, persistent fused kernels replayed from a "
-                           "HIP graph", "evals": ev}, **extra)
+              {"workload": ("batched SHADE: 2048 runs, D in {10,30,50,100}, NP = min(18 D, 200), "
+                            "budget 10000 D, p = 0.1, H = 6" if a.workload == "c4" else
+                            "batched L-SHADE: 2048 runs, D in {10,30,50,100}, NP from min(18 D, 200) "
+                            "down to 4, budget 10000 D, p = 0.11, H = 6, archive 2.6 NP") +
+                           ", persistent fused kernels replayed from a HIP graph", "evals": ev}, **extra)
     elif a.workload == "c5":
         out = {}
         for prec, name in ((S.SPLIT_BF16, "split_bf16"), (S.FP32, "fp32")):

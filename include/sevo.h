@@ -18,7 +18,10 @@
  *   - sevo_run: the Experiment module's independent runs (Sec. 2.4, Listing
  *     3's evo_bench) for DE, PSO and SHADE (Listing 1) at once, each with a
  *     function-evaluation budget (Listing 4's loop) and the best-so-far
- *     record every 200 evaluations (Sec. 2.4, Sec. 3.2).
+ *     record every 200 evaluations (Sec. 2.4, Sec. 3.2); also L-SHADE, the
+ *     SHADE variant with an external archive and population size reduction
+ *     that the DE module's archive and reduction mechanisms make (Sec. 2.2,
+ *     and the L-SHADE family of Sec. 4).
  *
  * Conventions shared by every call
  *   - Status: every call returns SEVO_OK (0) or a negative SEVO_E* code and
@@ -77,7 +80,7 @@ enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFE
  * state and errors are double. */
 enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
 
-enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2 };
+enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3 };
 
 typedef struct sevo_ctx sevo_ctx;   /* opaque, library-owned */
 
@@ -247,8 +250,11 @@ typedef struct {
     int64_t budget;        /* function evaluations; whole generations are run */
     double F, CR;          /* DE */
     double w, c1, c2, vmax;/* PSO */
-    double p;              /* SHADE: pbest fraction (top max(2, round(p NP))) */
-    int32_t H;             /* SHADE: memory size (1 .. 16) */
+    double p;              /* SHADE, L-SHADE: pbest fraction (top max(2, round(p NP))) */
+    int32_t H;             /* SHADE, L-SHADE: memory size (1 .. 16) */
+    double r_arc;          /* L-SHADE: archive bound round(r_arc NP), 0 .. 2.9 (2.6 in L-SHADE) */
+    int32_t np_min;        /* L-SHADE: population size at the budget, 4 .. np */
+    int32_t reserved;      /* 0 */
 } sevo_run_desc;
 
 typedef struct {
@@ -263,7 +269,15 @@ typedef struct {
 
 /* Run n_runs independent runs to their budgets in persistent fused kernels
  * (precision FP32: single-precision state, double-precision shift and final
- * check; FP64: everything double).
+ * check; FP64: everything double, DE and PSO only).
+ *   L-SHADE (Tanabe and Fukunaga, CEC 2014): SHADE's draws (a terminal CR
+ *   memory gives CR = 0) with r2 from the population and the archive; every
+ *   strictly improved parent enters the archive in index order (appended
+ *   below round(r_arc NP), else written over a random member); both memories
+ *   take the weighted Lehmer mean, the CR memory becoming terminal when all
+ *   successful CR are 0; after each generation the population shrinks to
+ *   round((np_min - np) FE / budget + np) by dropping the worst (the rest keep
+ *   their order) and the archive to its new bound by random removals.
  *   results  device, [n_runs] sevo_run_result.
  *   trace    optional device [n_runs][trace_len] float: best error after
  *            200 (k+1) evaluations, NaN where the run made fewer.

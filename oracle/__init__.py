@@ -53,6 +53,7 @@ class RunDesc(C.Structure):
         ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
         ("p", C.c_double), ("H", C.c_int32),
         ("r_arc", C.c_double), ("np_min", C.c_int32),
+        ("topology", C.c_int32), ("velocity", C.c_int32),
     ]
 
 
@@ -123,6 +124,9 @@ def lib():
         L.orc_lshade_memory_update.argtypes = [C.c_int32, dp, dp, ip, C.c_int32, dp, dp, dp]
         L.orc_lshade_generation.argtypes = [pp, dp, dp, C.POINTER(_LShadeState), C.c_double, C.c_double,
                                             C.c_int32, C.c_uint32, C.c_uint64, C.c_uint32, dp, dp, ip]
+        L.orc_pso_variant_iteration.argtypes = [pp, dp, dp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                                C.c_double, C.c_double, C.c_double, C.c_uint32, C.c_uint64,
+                                                C.c_uint32, dp, dp, dp, dp, dp, ip]
         L.orc_run.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
                               dp, C.c_int64, dp]
         for name in ("orc_schwefel_s", "orc_schwefel_c", "orc_schwefel_lambda"):
@@ -339,6 +343,25 @@ def shade_memory_update(MF, MCR, pos, SF, SCR, dS):
     lib().orc_shade_memory_update(MF.shape[0], _d(MF), _d(MCR), _p(posa, C.c_int32),
                                   SF.shape[0], _d(SF), _d(SCR), _d(dS))
     return MF, MCR, int(posa[0])
+
+
+def pso_variant_iteration(func, lb, ub, o, M, X, V, P, eX, eP, topology, velocity, w, c1, c2, vmax,
+                          run_uid, seed, t):
+    """One PSO iteration with the given topology (0 global, 1 ring) and
+    velocity update (0 inertia, 1 spherical); returns the new (X, V, P, eX,
+    eP) and the neighbourhood bests used."""
+    X, V, P = (np.ascontiguousarray(a, dtype=np.float64).copy() for a in (X, V, P))
+    eX, eP = (np.ascontiguousarray(a, dtype=np.float64).copy() for a in (eX, eP))
+    np_, dim = X.shape
+    pb = _Problem(func, dim, lb, ub)
+    lbest = np.zeros(np_, dtype=np.int32)
+    rc = lib().orc_pso_variant_iteration(C.byref(pb), _d(np.ascontiguousarray(o, dtype=np.float64)),
+                                         _d(np.ascontiguousarray(M, dtype=np.float64)), np_, topology, velocity,
+                                         w, c1, c2, vmax, run_uid, C.c_uint64(seed), t, _d(X), _d(V), _d(P),
+                                         _d(eX), _d(eP), _p(lbest, C.c_int32))
+    if rc != 0:
+        raise ValueError("orc_pso_variant_iteration failed")
+    return X, V, P, eX, eP, lbest
 
 
 def lshade_np(np_init, np_min, budget, fe):

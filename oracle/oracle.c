@@ -514,6 +514,94 @@ int orc_pso_iteration(const orc_problem *pb, const double *o, const double *M, i
     return 0;
 }
 
+/* Best personal best of i's neighbourhood: i itself for the global-best
+ * topology is replaced by the global best; ring: {i-1, i, i+1} mod np. */
+static int32_t neighbourhood_best(const double *eP, int32_t np, int32_t i, int32_t topology, int32_t g)
+{
+    if (topology == 0) return g;
+    int32_t cand[3] = { (i + np - 1) % np, i, (i + 1) % np };
+    int32_t best = cand[0];
+    for (int k = 1; k < 3; ++k) {
+        const int32_t c = cand[k];
+        if (key_of(eP[c]) < key_of(eP[best]) || (key_of(eP[c]) == key_of(eP[best]) && c < best)) best = c;
+    }
+    return best;
+}
+
+int orc_pso_variant_iteration(const orc_problem *pb, const double *o, const double *M, int32_t np,
+                              int32_t topology, int32_t velocity, double w, double c1, double c2,
+                              double vmax, uint32_t run_uid, uint64_t seed, uint32_t t,
+                              double *X, double *V, double *P, double *eX, double *eP, int32_t *lbest)
+{
+    const int D = pb->dim;
+    if (np < 1 || topology < 0 || topology > 1 || velocity < 0 || velocity > 1) return -1;
+    const size_t uD = (size_t)D;
+    /* neighbourhood bests from the personal bests before this iteration */
+    int32_t *l = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
+    double *Pold = (double *)malloc(sizeof(double) * (size_t)np * uD);
+    double *G = (double *)malloc(sizeof(double) * uD * 2);
+    if (!l || !Pold || !G) { free(l); free(Pold); free(G); return -1; }
+    const int32_t g = argmin_lowest(eP, np);
+    for (int i = 0; i < np; ++i) l[i] = neighbourhood_best(eP, np, i, topology, g);
+    if (lbest) memcpy(lbest, l, sizeof(int32_t) * (size_t)np);
+    memcpy(Pold, P, sizeof(double) * (size_t)np * uD);
+    double *z = G + uD;
+    uint32_t wd[4];
+    for (int i = 0; i < np; ++i) {
+        double *x = X + (size_t)i * uD, *v = V + (size_t)i * uD;
+        const double *p = Pold + (size_t)i * uD, *pl = Pold + (size_t)l[i] * uD;
+        if (velocity == 0) {
+            for (int j = 0; j < D; ++j) {
+                if (j % 2 == 0) draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_PSO_R, (uint32_t)(j / 2), 0, wd);
+                const double r1 = orc_u24(wd[2 * (j % 2)]), r2 = orc_u24(wd[2 * (j % 2) + 1]);
+                v[j] = w * v[j] + c1 * r1 * (p[j] - x[j]) + c2 * r2 * (pl[j] - x[j]);
+            }
+        } else {
+            /* centre of gravity of x, p' and l' (or of x and p' when the
+               particle is its own neighbourhood best) */
+            double R2 = 0.0, z2 = 0.0;
+            for (int j = 0; j < D; ++j) {
+                const double pp = x[j] + c1 * (p[j] - x[j]);
+                if (l[i] == i) {
+                    G[j] = (x[j] + pp) / 2.0;
+                } else {
+                    const double lp = x[j] + c1 * (pl[j] - x[j]);
+                    G[j] = (x[j] + pp + lp) / 3.0;
+                }
+                R2 += (G[j] - x[j]) * (G[j] - x[j]);
+                if (j % 2 == 0) draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_PSO_S, (uint32_t)(j / 2), 0, wd);
+                const double rad = sqrt(-2.0 * log(1.0 - orc_u24(wd[0])));
+                const double ang = 2.0 * M_PI * orc_u24(wd[1]);
+                z[j] = j % 2 == 0 ? rad * cos(ang) : rad * sin(ang);
+                z2 += z[j] * z[j];
+            }
+            uint32_t wr[4];
+            draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_PSO_SR, 0, 0, wr);
+            const double r = sqrt(R2) * pow(orc_u24(wr[0]), 1.0 / (double)D);
+            const double sc = z2 > 0.0 ? r / sqrt(z2) : 0.0;
+            for (int j = 0; j < D; ++j) v[j] = w * v[j] + (G[j] + sc * z[j]) - x[j];
+        }
+        for (int j = 0; j < D; ++j) {
+            double vj = v[j];
+            if (vj > vmax) vj = vmax;
+            if (vj < -vmax) vj = -vmax;
+            double xj = x[j] + vj;
+            if (xj < pb->lb) { xj = pb->lb; vj = 0.0; }
+            else if (xj > pb->ub) { xj = pb->ub; vj = 0.0; }
+            x[j] = xj;
+            v[j] = vj;
+        }
+    }
+    free(l); free(Pold); free(G);
+    orc_error_aos(pb->func, D, o, M, X, np, eX);
+    for (int i = 0; i < np; ++i)
+        if (key_of(eX[i]) < key_of(eP[i])) {
+            memcpy(P + (size_t)i * uD, X + (size_t)i * uD, sizeof(double) * uD);
+            eP[i] = eX[i];
+        }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* SHADE. */
 
@@ -871,8 +959,15 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
         for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
         while (rec.fe < d->budget) {
             ++gens;
-            orc_pso_iteration(&pb, o, M, np, d->w, d->c1, d->c2, d->vmax, d->run_uid, seed,
-                              (uint32_t)gens, X, V, P, eX, eP, &g);
+            if (d->topology == 0 && d->velocity == 0)
+                orc_pso_iteration(&pb, o, M, np, d->w, d->c1, d->c2, d->vmax, d->run_uid, seed,
+                                  (uint32_t)gens, X, V, P, eX, eP, &g);
+            else if (orc_pso_variant_iteration(&pb, o, M, np, d->topology, d->velocity, d->w, d->c1, d->c2,
+                                               d->vmax, d->run_uid, seed, (uint32_t)gens, X, V, P, eX, eP,
+                                               NULL) != 0) {
+                rc = -1;
+                break;
+            }
             for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
         }
     } else if (d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE) {

@@ -37,6 +37,7 @@ enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 
 enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
        ORC_TAG_PSO_R = 4, ORC_TAG_SHADE_P = 5, ORC_TAG_SHADE_C = 6,
        ORC_TAG_SHADE_D = 7, ORC_TAG_LSHADE_A = 8, ORC_TAG_LSHADE_S = 9,
+       ORC_TAG_PSO_S = 10, ORC_TAG_PSO_SR = 11,
        ORC_TAG_SHIFT_O = 16, ORC_TAG_ROT_N = 17 };
 
 typedef struct {
@@ -105,6 +106,25 @@ int orc_pso_iteration(const orc_problem *pb, const double *o, const double *M, i
                       double w, double c1, double c2, double vmax,
                       uint32_t run_uid, uint64_t seed, uint32_t t,
                       double *X, double *V, double *P, double *eX, double *eP, int32_t *g);
+
+/* ---- PSO variants of the PSO module (Listing 1's spherical velocity update
+ * with ring topology) ----
+ * topology 0: global best; 1: ring, the neighbourhood of i being
+ * {i-1, i, i+1} (mod np) and l_i its best personal best (lowest index among
+ * equal errors).  velocity 0: inertia weight, v = w v + c1 r1 (p - x) +
+ * c2 r2 (p_l - x); velocity 1: spherical (SPSO-2011, Clerc): with
+ * p' = x + c1 (p - x), l' = x + c1 (p_l - x), the centre G = (x + p' + l') / 3,
+ * or (x + p') / 2 when l_i = i; x' uniform in the ball of centre G and
+ * radius |G - x| (Gaussian direction, radius |G - x| u^(1/D)); v = w v + x' - x.
+ * Both: |v_j| <= vmax, x += v, a coordinate leaving the box is put on the
+ * bound with its velocity zeroed; pbest on strict improvement.
+ * Draws: inertia as orc_pso_iteration (tag PSO_R); spherical: tag PSO_S
+ * block b gives the normals of dimensions 2b, 2b+1 by Box-Muller on
+ * (u24(w0), u24(w1)), tag PSO_SR word 0 the radius uniform. */
+int orc_pso_variant_iteration(const orc_problem *pb, const double *o, const double *M, int32_t np,
+                              int32_t topology, int32_t velocity, double w, double c1, double c2,
+                              double vmax, uint32_t run_uid, uint64_t seed, uint32_t t,
+                              double *X, double *V, double *P, double *eX, double *eP, int32_t *lbest);
 
 /* ---- SHADE (success-history adaptation, current-to-pbest/1, no archive) ---- */
 /* Per-individual draws: idx[i*6 + k] = (memory slot, pbest index, r1, r2,
@@ -179,6 +199,8 @@ typedef struct {
     int32_t H;             /* SHADE / L-SHADE: memory size */
     double r_arc;          /* L-SHADE: archive bound per individual */
     int32_t np_min;        /* L-SHADE: final population size */
+    int32_t topology;      /* PSO: 0 global best, 1 ring */
+    int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical */
 } orc_run_desc;
 
 typedef struct {

@@ -71,16 +71,19 @@ __device__ __forceinline__ T cross_repair(uint32_t word, uint32_t thr, int j, in
 }
 
 // SHADE per-individual parameters: memory slot k, CR ~ N(M_CR[k], 0.1)
-// clipped to [0, 1], F ~ Cauchy(M_F[k], 0.1) redrawn while <= 0 (at most
-// 64 draws, then F = M_F[k]) and capped at 1; pbest drawn from the top
-// pnum of the ranking; r1 != i, r2 not in {i, r1}; jrand.
+// clipped to [0, 1] (CR = 0 when the slot holds the terminal value, a
+// negative number, which only L-SHADE sets), F ~ Cauchy(M_F[k], 0.1)
+// redrawn while <= 0 (at most 64 draws, then F = M_F[k]) and capped at 1;
+// pbest drawn from the top pnum of the ranking; r1 != i; r2 not in {i, r1}
+// among n2 candidates (np for SHADE; np + archive size for L-SHADE, where
+// values >= np index the archive); jrand.
 struct ShadeDraw {
     int k, pbest_rank, r1, r2, jrand, retries;
     float F, CR;
 };
 
 __device__ __forceinline__ ShadeDraw shade_draw(uint32_t run_uid, uint32_t seed32, uint32_t t, int i,
-                                                int np, int dim, int H, int pnum, const float *MF,
+                                                int np, int n2, int dim, int H, int pnum, const float *MF,
                                                 const float *MCR)
 {
     ShadeDraw d;
@@ -90,7 +93,7 @@ __device__ __forceinline__ ShadeDraw shade_draw(uint32_t run_uid, uint32_t seed3
     const float u1 = u24f(wp.y), u2 = u24f(wp.z);
     const float nrm = sqrtf(-2.f * logf(1.f - u1)) * cospif(2.f * u2);
     float cr = MCR[d.k] + 0.1f * nrm;
-    d.CR = fminf(fmaxf(cr, 0.f), 1.f);
+    d.CR = MCR[d.k] < 0.f ? 0.f : fminf(fmaxf(cr, 0.f), 1.f);
     float F = -1.f;
     int retries = 0;
     for (; retries < 64; ++retries) {
@@ -107,7 +110,7 @@ __device__ __forceinline__ ShadeDraw shade_draw(uint32_t run_uid, uint32_t seed3
     const int e1[1] = {i};
     d.r1 = pick_excluding<1>(wd.x, np, e1);
     const int e2[2] = {i, d.r1};
-    d.r2 = pick_excluding<2>(wd.y, np, e2);
+    d.r2 = pick_excluding<2>(wd.y, n2, e2);
     d.jrand = (int)range_map(wd.z, (uint32_t)dim);
     return d;
 }

@@ -32,6 +32,8 @@ enum Tag : uint32_t {
     TAG_SHADE_P = 5,  // SHADE: (memory slot, normal u1, normal u2, pbest)
     TAG_SHADE_C = 6,  // SHADE: Cauchy uniform in word 0, c3 = retry
     TAG_SHADE_D = 7,  // SHADE: (r1, r2, jrand, unused)
+    TAG_LSHADE_A = 8, // L-SHADE: archive slot of an improved parent when the archive is full
+    TAG_LSHADE_S = 9, // L-SHADE: k-th archive removal after a reduction (individual = k)
     TAG_SHIFT_O = 16, // instance shift: two 53-bit uniforms per block
     TAG_ROT_N = 17,   // instance rotation: one Box-Muller pair per block
 };

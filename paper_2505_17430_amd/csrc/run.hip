@@ -44,6 +44,11 @@ struct RunDev {
     const float *tab;
     const double *M64;
     float *X, *U, *V, *P, *bestx;   // workspace (X .. P unused when on chip)
+    // L-SHADE: pbest fraction and archive bound (double, as the schedule is
+    // computed), final population size, archive [dim][acap] in the workspace
+    double p, r_arc;
+    int32_t np_min, acap;
+    float *Arc;
     sevo_run_result *res;
     float *trace;
     int64_t trace_len;
@@ -130,10 +135,48 @@ __device__ __forceinline__ void prefix_min(const Team<WAVE> &t, float v, int idx
     pi = idx;
 }
 
+// Nearest integer, halves away from zero, of a non-negative double (the
+// C library's lround on the values used here).
+__device__ __forceinline__ int round_half_up(double x)
+{
+    const double f = floor(x);
+    return (int)(x - f >= 0.5 ? f + 1.0 : f);
+}
+
+// L-SHADE population size after fe of budget evaluations.
+__device__ __forceinline__ int lshade_np(int np_init, int np_min, int64_t budget, int64_t fe)
+{
+    const double v = (double)(np_min - np_init) * (double)fe / (double)budget + (double)np_init;
+    return min(max(round_half_up(v), np_min), np_init);
+}
+
+// Exclusive count of the set flags before this member, in member order;
+// total receives the count over the team.
+template <bool WAVE>
+__device__ __forceinline__ int team_exclusive_count(const Team<WAVE> &t, bool flag, int *sWc, int &total)
+{
+    const unsigned long long m = __ballot(flag);
+    int excl = __popcll(m & ((1ull << t.lane) - 1ull));
+    total = __popcll(m);
+    if constexpr (!WAVE) {
+        if (t.lane == 0) sWc[t.wave] = total;
+        __syncthreads();
+        int before = 0, all = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < t.wave) before += sWc[w];
+            all += sWc[w];
+        }
+        __syncthreads();
+        excl += before;
+        total = all;
+    }
+    return excl;
+}
+
 // Sums over the team of N doubles per member, in a fixed order (lanes by a
 // shuffle tree, then waves 0..3 in order); every member gets the sums.
 template <int N, bool WAVE>
-__device__ __forceinline__ void team_sums(const Team<WAVE> &t, double (&v)[N], double *sRed /* [4 * N] */)
+__device__ __forceinline__ void team_sums(const Team<WAVE> &t, double (&v)[N], double (&sRed)[4 * N])
 {
 #pragma unroll
     for (int k = 0; k < N; ++k)
@@ -153,19 +196,19 @@ __device__ __forceinline__ void team_sums(const Team<WAVE> &t, double (&v)[N], d
 // Errors of the np points Y ([dim][npp], in LDS when ONCHIP, else in the
 // workspace) into eY (LDS): the team's waves take 16-point tiles in turn.
 template <int KS, bool ONCHIP, bool WAVE>
-__device__ __forceinline__ void eval_pop(const Team<WAVE> &t, const RunDev &R, const float *Y, float *eY,
+__device__ __forceinline__ void eval_pop(const Team<WAVE> &t, const RunDev &R, int np, const float *Y, float *eY,
                                          const float *sA, const double *sO, const float *sT, const Consts &K)
 {
     const int lane = t.lane;
     const int kq = lane >> 4, pc = lane & 15;
-    const int ntile = (R.np + 15) / 16;
+    const int ntile = (np + 15) / 16;
     constexpr int NW = Team<WAVE>::NW;
     // from the workspace, the next tile's loads are in flight while the
     // current one is computed (while the extra registers are affordable)
     constexpr bool PF = !ONCHIP && KS <= 13;
     auto load = [&](float (&dst)[KS][1], int p0) {
-        if constexpr (ONCHIP) load_raw_lds<KS, 1>(dst, Y, R.npp, R.dim, R.np, p0, kq, pc);
-        else load_raw<KS, 1>(dst, gin<float>(Y), R.npp, R.dim, R.np, p0, kq, pc);
+        if constexpr (ONCHIP) load_raw_lds<KS, 1>(dst, Y, R.npp, R.dim, np, p0, kq, pc);
+        else load_raw<KS, 1>(dst, gin<float>(Y), R.npp, R.dim, np, p0, kq, pc);
     };
     float b[KS][1], bn[KS][1];
     if (t.wave < ntile) load(b, t.wave * 16);
@@ -173,14 +216,14 @@ __device__ __forceinline__ void eval_pop(const Team<WAVE> &t, const RunDev &R, c
         const int p0 = ct * 16, nx = ct + NW;
         if constexpr (PF)
             if (nx < ntile) load(bn, nx * 16);
-        shift_raw<KS, 1>(b, R.dim, R.np, p0, kq, pc, sO);
+        shift_raw<KS, 1>(b, R.dim, np, p0, kq, pc, sO);
         switch (R.func) {
-        case ELLIPSOID: tile_body<ELLIPSOID, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
-        case ROSENBROCK: tile_body<ROSENBROCK, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
-        case RASTRIGIN: tile_body<RASTRIGIN, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
-        case SCHWEFEL: tile_body<SCHWEFEL, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
-        case GRIEWANK: tile_body<GRIEWANK, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
-        default: tile_body<ACKLEY, KS, 1>(b, sA, sT, lane, R.dim, R.np, p0, K.kf, eY); break;
+        case ELLIPSOID: tile_body<ELLIPSOID, KS, 1>(b, sA, sT, lane, R.dim, np, p0, K.kf, eY); break;
+        case ROSENBROCK: tile_body<ROSENBROCK, KS, 1>(b, sA, sT, lane, R.dim, np, p0, K.kf, eY); break;
+        case RASTRIGIN: tile_body<RASTRIGIN, KS, 1>(b, sA, sT, lane, R.dim, np, p0, K.kf, eY); break;
+        case SCHWEFEL: tile_body<SCHWEFEL, KS, 1>(b, sA, sT, lane, R.dim, np, p0, K.kf, eY); break;
+        case GRIEWANK: tile_body<GRIEWANK, KS, 1>(b, sA, sT, lane, R.dim, np, p0, K.kf, eY); break;
+        default: tile_body<ACKLEY, KS, 1>(b, sA, sT, lane, R.dim, np, p0, K.kf, eY); break;
         }
         if (nx < ntile) {
             if constexpr (PF) {
@@ -248,8 +291,11 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     __shared__ uint32_t sThrA[256];
     __shared__ float sEXA[256], sEUA[256], sEPA[256];   // errors of x, of trials / new positions, of pbests
     __shared__ float sWv[4];
-    __shared__ int sWi[4];
-    __shared__ double sRed[4 * 5];
+    __shared__ int sWi[4], sWc[4];
+    __shared__ int sOwnA[768];            // L-SHADE: archive slot owners (192 per wave team)
+    __shared__ int sNaA[4], sCutA[4];     // L-SHADE: archive size, slot of a removal
+    constexpr int NSUM = 7;               // sums of the DE-family memory update
+    __shared__ double sRed[4 * NSUM];
     __shared__ double sZA[WAVE ? 4 : 1][128];
     // per-team scalars
     __shared__ float sMFA[4][16], sMCRA[4][16];
@@ -272,8 +318,10 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
 
     const RunDev R = runs[run_index];
     if (WAVE && R.np == 0) return;   // empty slot: no barrier follows for wave teams
-    const int D = R.dim, np = R.np, npp = R.npp;
-    const bool pso = R.algo == SEVO_ALGO_PSO, shade = R.algo == SEVO_ALGO_SHADE;
+    const int D = R.dim, npp = R.npp;
+    int np = R.np;   // L-SHADE shrinks it
+    const bool pso = R.algo == SEVO_ALGO_PSO, lshade = R.algo == SEVO_ALGO_LSHADE;
+    const bool shade = R.algo == SEVO_ALGO_SHADE || lshade;
     float *X, *U, *V, *P;
     if constexpr (ONCHIP) {
         X = sDyn + (WAVE ? s * dyn_stride : 0);
@@ -295,7 +343,11 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     float *sMF = sMFA[s], *sMCR = sMCRA[s];
     double *sZ = sZA[WAVE ? s : 0];
     if (tid < 16) { sMF[tid] = 0.5f; sMCR[tid] = 0.5f; }
-    if (tid == 0) { sPosA[s] = 0; sGA[s] = 0; sBestA[s] = INFINITY; sBestBA[s] = INFINITY; sCopyA[s] = -1; }
+    if (tid == 0) {
+        sPosA[s] = 0; sGA[s] = 0; sBestA[s] = INFINITY; sBestBA[s] = INFINITY; sCopyA[s] = -1;
+        sNaA[s] = 0;
+    }
+    int *sOwn = sOwnA + (WAVE ? s * 192 : 0);
 
     // Element loops: the team's wave w takes coordinate blocks w, w + NW, ...;
     // its lanes take individuals, so every access to the [D][npp] state is
@@ -371,7 +423,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
         t.sync();
     };
 
-    eval_pop<KS, ONCHIP>(t, R, X, sEX, sA, sO, sT, K);
+    eval_pop<KS, ONCHIP>(t, R, np, X, sEX, sA, sO, sT, K);
     t.sync();
     record(X, sEX);
     if (pso) {
@@ -430,7 +482,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                     }
                 }
             t.sync();
-            eval_pop<KS, ONCHIP>(t, R, X, sEX, sA, sO, sT, K);
+            eval_pop<KS, ONCHIP>(t, R, np, X, sEX, sA, sO, sT, K);
             t.sync();
             record(X, sEX);
             if (tid < np) {
@@ -462,7 +514,9 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
             if (tid < np) {
                 const int i = tid;
                 if (shade) {
-                    const ShadeDraw d = shade_draw(R.run_uid, seed32, tg, i, np, D, R.H, R.pnum, sMF, sMCR);
+                    const int pnum = lshade ? min(max(round_half_up(R.p * (double)np), 2), np) : R.pnum;
+                    const int n2 = lshade ? np + sNaA[s] : np;
+                    const ShadeDraw d = shade_draw(R.run_uid, seed32, tg, i, np, n2, D, R.H, pnum, sMF, sMCR);
                     sF[i] = d.F;
                     sCR[i] = d.CR;
                     sFi[i] = d.F;
@@ -496,10 +550,12 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                     for (int c = 0; c < DE_CH; ++c)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const int row = min((jb0 + c) * 4 + e, D - 1) * npp;
+                            const int jj = min((jb0 + c) * 4 + e, D - 1), row = jj * npp;
                             xi[c][e] = X[row + i];
                             xa[c][e] = X[row + ia];
-                            xb[c][e] = X[row + ib];
+                            // L-SHADE's r2 may index the archive (values >= np)
+                            const float *pb = ib < np ? X + row + ib : R.Arc + (size_t)jj * R.acap + (ib - np);
+                            xb[c][e] = *pb;
                             xc[c][e] = X[row + ic];
                         }
 #pragma unroll
@@ -523,36 +579,128 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                     }
                 }
             t.sync();
-            eval_pop<KS, ONCHIP>(t, R, U, sEU, sA, sO, sT, K);
+            eval_pop<KS, ONCHIP>(t, R, np, U, sEU, sA, sO, sT, K);
             t.sync();
             record(U, sEU);
-            double st[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // sum dl, dl CR, dl F^2, dl F, successes
+            // sums of dl, dl CR, dl CR^2, dl F^2, dl F, successes, successes with CR > 0
+            double st[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            bool succ = false;
             if (tid < np) {
                 const float ku = err_key(sEU[tid]), kx = err_key(sEX[tid]);
-                if (shade && ku < kx) {
+                succ = ku < kx;
+                if (shade && succ) {
                     double dl = (double)kx - (double)ku;
                     if (!(dl <= 1e30)) dl = 1e30;
+                    const double cr = sCR[tid], f = sF[tid];
                     st[0] = dl;
-                    st[1] = dl * sCR[tid];
-                    st[2] = dl * sF[tid] * sF[tid];
-                    st[3] = dl * sF[tid];
-                    st[4] = 1.0;
+                    st[1] = dl * cr;
+                    st[2] = dl * cr * cr;
+                    st[3] = dl * f * f;
+                    st[4] = dl * f;
+                    st[5] = 1.0;
+                    st[6] = cr > 0.0 ? 1.0 : 0.0;
                 }
-                const bool rep = ku <= kx;
+            }
+            if (lshade) {
+                // improved parents into the archive, in index order: appended
+                // below the bound, else over a random member; where several
+                // land on one slot the highest index wins (it came last)
+                const int amax = round_half_up(R.r_arc * (double)np), na = sNaA[s];
+                int total;
+                const int k = team_exclusive_count(t, succ, sWc, total);
+                int at = -1;
+                if (succ) {
+                    if (na + k < amax) at = na + k;
+                    else if (amax > 0)
+                        at = (int)range_map(draw(R.run_uid, seed32, tg, (uint32_t)tid, TAG_LSHADE_A, 0).x,
+                                            (uint32_t)amax);
+                }
+                for (int q = tid; q < amax; q += TS) sOwn[q] = -1;
+                t.sync();
+                if (at >= 0) atomicMax(&sOwn[at], tid);
+                t.sync();
+                if (tid < np) sDa[tid] = at >= 0 && sOwn[at] == tid ? at : -1;
+                t.sync();
+                for (int j = wave; j < D; j += NW)
+                    for (int i = lane; i < np; i += 64) {
+                        const int slot = sDa[i];
+                        if (slot >= 0) R.Arc[(size_t)j * R.acap + slot] = X[j * npp + i];
+                    }
+                t.sync();
+                if (tid == 0) sNaA[s] = min(amax, na + total);
+            }
+            if (tid < np) {
+                const bool rep = err_key(sEU[tid]) <= err_key(sEX[tid]);
                 if (rep) sEX[tid] = sEU[tid];
                 sFlag[tid] = rep ? 1 : 0;
             }
             t.sync();
             copy_flagged(X, U);
             if (shade) {
-                team_sums<5>(t, st, sRed);
-                if (tid == 0 && st[4] > 0.0) {
+                team_sums<NSUM>(t, st, sRed);
+                if (tid == 0 && st[5] > 0.0) {
                     const int pos = sPosA[s];
-                    sMCR[pos] = (float)(st[1] / st[0]);
-                    sMF[pos] = (float)(st[2] / st[3]);
+                    if (lshade)   // weighted Lehmer mean; terminal value kept or set
+                        sMCR[pos] = (sMCR[pos] < 0.f || st[6] == 0.0) ? -1.f : (float)(st[2] / st[1]);
+                    else          // SHADE: weighted arithmetic mean
+                        sMCR[pos] = (float)(st[1] / st[0]);
+                    sMF[pos] = (float)(st[3] / st[4]);
                     sPosA[s] = (pos + 1) % R.H;
                 }
                 t.sync();
+            }
+            if (lshade) {
+                // linear population size reduction: the best nn stay, in index order
+                const int nn = min(lshade_np(R.np, R.np_min, R.budget, fe + np), np);
+                if (nn < np) {
+                    if (tid < np) {
+                        const uint32_t bits = __float_as_uint(err_key(sEX[tid]));
+                        const uint32_t ord = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
+                        sKey[tid] = ((unsigned long long)ord << 32) | (uint32_t)tid;
+                    }
+                    t.sync();
+                    bool keep = false;
+                    if (tid < np) {
+                        const unsigned long long key = sKey[tid];
+                        int rank = 0;
+                        for (int q = 0; q < np; ++q) rank += sKey[q] < key ? 1 : 0;
+                        keep = rank < nn;
+                    }
+                    int kept;
+                    const int to = team_exclusive_count(t, keep, sWc, kept);
+                    if (tid < np) sDb[tid] = keep ? to : -1;
+                    t.sync();
+                    for (int j = wave; j < D; j += NW)
+                        for (int i = lane; i < np; i += 64) {
+                            const int d = sDb[i];
+                            if (d >= 0) U[j * npp + d] = X[j * npp + i];
+                        }
+                    if (tid < np && keep) sEU[to] = sEX[tid];
+                    t.sync();
+                    float *tx = X; X = U; U = tx;
+                    float *te = sEX; sEX = sEU; sEU = te;
+                    // the archive down to its new bound by random removals,
+                    // the last member moving into the freed slot
+                    const int amax2 = round_half_up(R.r_arc * (double)nn);
+                    int na = sNaA[s];
+                    for (uint32_t k = 0; na > amax2; ++k) {
+                        if (tid == 0)
+                            sCutA[s] = (int)range_map(draw(R.run_uid, seed32, tg, k, TAG_LSHADE_S, 0).x,
+                                                      (uint32_t)na);
+                        t.sync();
+                        const int cut = sCutA[s];
+                        if (cut != na - 1)
+                            for (int j = tid; j < D; j += TS)
+                                R.Arc[(size_t)j * R.acap + cut] = R.Arc[(size_t)j * R.acap + na - 1];
+                        t.sync();
+                        --na;
+                    }
+                    if (tid == 0) sNaA[s] = na;
+                    t.sync();
+                    fe += np;
+                    np = nn;
+                    continue;
+                }
             }
         }
         fe += np;
@@ -623,6 +771,14 @@ int32_t shade_pnum(double p, int32_t np)
     return (int32_t)k;
 }
 
+// Archive slots of an L-SHADE run (its bound at the initial population,
+// plus one); 0 for the other algorithms.
+int archive_cap(const sevo_run_desc &d)
+{
+    if (d.algo != SEVO_ALGO_LSHADE) return 0;
+    return (int)std::lround(d.r_arc * (double)d.np) + 1;
+}
+
 int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision, int64_t trace_len,
                   const float *trace, const double *best_x, int max_dim)
 {
@@ -635,7 +791,8 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
         const sevo_problem &p = d.prob;
         if (p.func < 0 || p.func >= NFUNC || p.dim < 2 || p.dim > MAX_DIM || !(p.lb < p.ub))
             return set_error(ctx, SEVO_EINVAL, "run has an invalid problem");
-        if (d.algo != SEVO_ALGO_DE && d.algo != SEVO_ALGO_PSO && d.algo != SEVO_ALGO_SHADE)
+        if (d.algo != SEVO_ALGO_DE && d.algo != SEVO_ALGO_PSO && d.algo != SEVO_ALGO_SHADE &&
+            d.algo != SEVO_ALGO_LSHADE)
             return set_error(ctx, SEVO_EINVAL, "unknown algorithm");
         const int min_np = d.algo == SEVO_ALGO_PSO ? 1 : 4;
         if (d.np < min_np || d.np > RUN_MAX_NP) return set_error(ctx, SEVO_EINVAL, "np outside [4 (1 for PSO), 256]");
@@ -644,12 +801,15 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             return set_error(ctx, SEVO_EINVAL, "DE needs finite F and CR in [0, 1]");
         if (d.algo == SEVO_ALGO_PSO && !(d.vmax > 0))
             return set_error(ctx, SEVO_EINVAL, "PSO needs vmax > 0");
-        if (d.algo == SEVO_ALGO_SHADE && (d.H < 1 || d.H > 16 || !(d.p > 0 && d.p <= 1)))
+        if ((d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE) &&
+            (d.H < 1 || d.H > 16 || !(d.p > 0 && d.p <= 1)))
             return set_error(ctx, SEVO_EINVAL, "SHADE needs H in [1, 16] and p in (0, 1]");
+        if (d.algo == SEVO_ALGO_LSHADE && (d.np_min < 4 || d.np_min > d.np || !(d.r_arc >= 0 && d.r_arc <= 2.9)))
+            return set_error(ctx, SEVO_EINVAL, "L-SHADE needs np_min in [4, np] and r_arc in [0, 2.9]");
         if (best_x && max_dim < p.dim) return set_error(ctx, SEVO_EINVAL, "max_dim < dim");
         if (precision == SEVO_FP32 && p.dim > SMALL_D_MAX)
             return set_error(ctx, SEVO_EUNSUPPORTED, "fused runs support D <= 120");
-        if (precision == SEVO_FP64 && d.algo == SEVO_ALGO_SHADE)
+        if (precision == SEVO_FP64 && (d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision run path has DE and PSO");
     }
     return SEVO_OK;
@@ -721,7 +881,7 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         const size_t per_wg = (wave[r] ? 4 : 1) * dyn[r] * sizeof(float);
         onchip[r] = !force_ws && per_wg <= onchip_limit(ks_of((int)D), wave[r]) ? 1 : 0;
         off[r] = total;
-        total += (onchip[r] ? 0 : 4 * D * npp) + D;
+        total += (onchip[r] ? 0 : 4 * D * npp) + D + D * (size_t)archive_cap(runs[r]);
         total = (total + 63) & ~(size_t)63;
     }
     float *ws = nullptr;
@@ -769,6 +929,11 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
             R.X = b; R.U = b + DN; R.V = b + 2 * DN; R.P = b + 3 * DN;
             R.bestx = b + 4 * DN;
         }
+        R.p = d.p;
+        R.r_arc = d.r_arc;
+        R.np_min = d.np_min;
+        R.acap = archive_cap(d);
+        R.Arc = R.acap > 0 ? R.bestx + R.dim : nullptr;
         R.res = results;
         R.trace = trace;
         R.trace_len = trace_len;

@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
 FP64, FP32, SPLIT_BF16 = 0, 1, 2
-ALGO_DE, ALGO_PSO, ALGO_SHADE = 0, 1, 2
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE = 0, 1, 2, 3
 TRACE_EVERY = 200
 
 
@@ -70,7 +70,8 @@ class RunDesc(C.Structure):
                 ("algo", C.c_int32), ("np", C.c_int32), ("budget", C.c_int64),
                 ("F", C.c_double), ("CR", C.c_double),
                 ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
-                ("p", C.c_double), ("H", C.c_int32)]
+                ("p", C.c_double), ("H", C.c_int32),
+                ("r_arc", C.c_double), ("np_min", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RunResult(C.Structure):

@@ -39,16 +39,19 @@ def ctx():
 
 
 def desc(algo, func, dim, np_, budget, uid, inst=0, **kw):
-    d = dict(F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618, vmax=0.2 * (UB - LB), p=0.1, H=6)
+    d = dict(F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618, vmax=0.2 * (UB - LB), p=0.1, H=6,
+             r_arc=2.6, np_min=4)
+    if algo == S.ALGO_LSHADE:
+        d["p"] = 0.11
     d.update(kw)
     return S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, d["F"], d["CR"], d["w"],
-                     d["c1"], d["c2"], d["vmax"], d["p"], d["H"])
+                     d["c1"], d["c2"], d["vmax"], d["p"], d["H"], d["r_arc"], d["np_min"])
 
 
 def odesc(d):
     return dict(algo=d.algo, func=d.prob.func, dim=d.prob.dim, lb=d.prob.lb, ub=d.prob.ub,
                 instance=d.instance, run_uid=d.run_uid, np=d.np, budget=d.budget, F=d.F, CR=d.CR,
-                w=d.w, c1=d.c1, c2=d.c2, vmax=d.vmax, p=d.p, H=d.H)
+                w=d.w, c1=d.c1, c2=d.c2, vmax=d.vmax, p=d.p, H=d.H, r_arc=d.r_arc, np_min=d.np_min)
 
 
 def gpu_run(ctx, descs, precision=S.FP32, trace_len=0, max_dim=None):
@@ -171,6 +174,55 @@ def test_fused_shade_distribution(ctx):
     _dist_compare(ctx, S.ALGO_SHADE, S.ROSENBROCK, 10, 100, 100 * 151, 32)
 
 
+@pytest.mark.parametrize("func,dim,np_,budget,r_arc", [
+    (S.RASTRIGIN, 10, 180, 20000, 2.6), (S.SCHWEFEL, 30, 60, 9000, 1.4), (S.ACKLEY, 10, 40, 4000, 0.0),
+    (S.ELLIPSOID, 100, 200, 12000, 2.6)])
+def test_fused_lshade_fe_accounting(ctx, func, dim, np_, budget, r_arc):
+    """L-SHADE's population schedule: evaluations and generations exactly the
+    oracle's (whole generations, NP from the linear reduction)."""
+    d = desc(S.ALGO_LSHADE, func, dim, np_, budget, uid=51, r_arc=r_arc)
+    (g,), tr, _ = gpu_run(ctx, [d], trace_len=budget // 200 + 2)
+    o, _, _ = O.run(odesc(d), SEED, ISEED)
+    assert g["fes"] == o["fes"] and g["generations"] == o["generations"]
+    n_rec = g["fes"] // 200
+    assert np.all(np.diff(tr[0][:n_rec]) <= 0)
+    assert g["best_e32"] <= tr[0][0]
+
+
+def test_fused_lshade_distribution(ctx):
+    ge, oe = _dist_compare(ctx, S.ALGO_LSHADE, S.ROSENBROCK, 10, 100, 100 * 151, 32)
+    # the archive and reduction help: L-SHADE is not worse than SHADE on the
+    # same runs (medians, both on the GPU)
+    gs, _ = _dist_compare(ctx, S.ALGO_SHADE, S.ROSENBROCK, 10, 100, 100 * 151, 32)
+    assert np.median(ge) <= 1.5 * np.median(gs)
+
+
+@pytest.mark.parametrize("algo", [S.ALGO_SHADE, S.ALGO_LSHADE])
+@pytest.mark.parametrize("dim", [30, 100])
+def test_fused_shade_family_dimension_classes(ctx, algo, dim):
+    """C4-shaped runs (NP = min(18 D, 200), one workgroup per run) in the
+    larger dimension classes: the GPU's median final error is not worse than
+    the oracle's by more than half a decade (8 runs per function; a broken
+    memory update or archive shows up as a consistently worse median), and
+    within 1.5 decades either way."""
+    import concurrent.futures as cf
+    n, np_ = 24, min(18 * dim, 200)
+    funcs = [S.ELLIPSOID, S.RASTRIGIN, S.GRIEWANK]
+    descs = [desc(algo, funcs[r % 3], dim, np_, 1000 * dim, uid=2000 + r, inst=r % 2) for r in range(n)]
+    gres, _, _ = gpu_run(ctx, descs)
+    with cf.ThreadPoolExecutor(16) as ex:
+        ores = list(ex.map(lambda d: O.run(odesc(d), SEED, ISEED)[0], descs))
+    for g, o in zip(gres, ores):
+        assert g["fes"] == o["fes"] and g["generations"] == o["generations"]
+    for f in range(3):
+        ge = np.log10(np.array([g["best_e"] for g in gres[f::3]]) + 1e-12)
+        oe = np.log10(np.array([o["best_e"] for o in ores[f::3]]) + 1e-12)
+        say(f"  algo={algo} D={dim} func={funcs[f]} median log10 e: gpu {np.median(ge):.2f} "
+            f"oracle {np.median(oe):.2f}")
+        assert np.median(ge) - np.median(oe) < 0.5
+        assert abs(np.median(ge) - np.median(oe)) < 1.5
+
+
 def test_fused_mixed_batch_matches_single_runs(ctx):
     """Runs of different algorithms and dimensions in one call give the same
     results as the same runs alone (no cross-run interference)."""
@@ -192,7 +244,9 @@ def test_fused_placement_does_not_change_results(ctx, monkeypatch):
              desc(S.ALGO_PSO, S.GRIEWANK, 50, 40, 4000, uid=22),
              desc(S.ALGO_SHADE, S.ROSENBROCK, 30, 200, 6000, uid=23),
              desc(S.ALGO_SHADE, S.SCHWEFEL, 100, 200, 2000, uid=24),
-             desc(S.ALGO_PSO, S.ACKLEY, 10, 7, 500, uid=25)]
+             desc(S.ALGO_PSO, S.ACKLEY, 10, 7, 500, uid=25),
+             desc(S.ALGO_LSHADE, S.RASTRIGIN, 30, 150, 9000, uid=26),
+             desc(S.ALGO_LSHADE, S.GRIEWANK, 100, 200, 6000, uid=27)]
     r1, t1, b1 = gpu_run(ctx, descs, trace_len=30, max_dim=100)
     monkeypatch.setenv("SEVO_RUN_PLACEMENT", "workspace")
     r2, t2, b2 = gpu_run(ctx, descs, trace_len=30, max_dim=100)
@@ -209,7 +263,8 @@ def test_fused_team_does_not_change_results(ctx, monkeypatch):
     descs = [desc(algo, S.RASTRIGIN, 30, np_, 2500, uid=40 + k)
              for k, (algo, np_) in enumerate([(S.ALGO_DE, 50), (S.ALGO_PSO, 40), (S.ALGO_SHADE, 64),
                                               (S.ALGO_DE, 4), (S.ALGO_PSO, 1), (S.ALGO_SHADE, 20),
-                                              (S.ALGO_DE, 33), (S.ALGO_PSO, 64), (S.ALGO_DE, 17)])]
+                                              (S.ALGO_DE, 33), (S.ALGO_PSO, 64), (S.ALGO_DE, 17),
+                                              (S.ALGO_LSHADE, 64), (S.ALGO_LSHADE, 30)])]
     descs += [desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=60, inst=3),
               desc(S.ALGO_DE, S.ELLIPSOID, 100, 24, 1500, uid=61, inst=1),
               desc(S.ALGO_SHADE, S.GRIEWANK, 50, 100, 3000, uid=62, inst=2)]
@@ -231,3 +286,11 @@ def test_run_rejects_bad_arguments(ctx):
         ctx.run([desc(S.ALGO_SHADE, 0, 10, 20, 100, 1, H=0)], res)    # H = 0
     with pytest.raises(S.SevoError):
         ctx.run([desc(S.ALGO_DE, 0, 10, 300, 1000, 1)], res)          # NP > 256
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_LSHADE, 0, 10, 50, 1000, 1, np_min=3)], res)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_LSHADE, 0, 10, 50, 1000, 1, np_min=51)], res)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_LSHADE, 0, 10, 50, 1000, 1, r_arc=3.0)], res)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_LSHADE, 0, 10, 50, 1000, 1)], res, precision=S.FP64)

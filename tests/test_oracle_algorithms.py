@@ -411,3 +411,80 @@ def test_lshade_run_fe_accounting():
     assert res["fes"] == fe and res["generations"] == gens
     assert np.all(np.diff(trace[: fe // 200]) <= 0)
     assert res["best_e"] <= trace[0]
+
+
+# ------------------------------------------------------------------ PSO variants
+
+W_SPSO, C_SPSO = 1.0 / (2.0 * math.log(2.0)), 0.5 + math.log(2.0)
+
+
+def _swarm(func, D, np_, iters=3, uid=4):
+    o, M = O.instance(func, D, 0, ISEED)
+    st = O.pso_init(func, LB, UB, o, M, np_, uid, SEED)
+    for t in range(1, iters + 1):
+        st = O.pso_iteration(func, LB, UB, o, M, st, 0.7298, 1.49618, 1.49618, 40.0, uid, SEED, t)
+    return o, M, st
+
+
+def test_pso_variant_global_inertia_is_the_classic_update():
+    func, D, np_ = O.GRIEWANK, 7, 30
+    o, M, st = _swarm(func, D, np_)
+    ref = O.pso_iteration(func, LB, UB, o, M, st, 0.7298, 1.49618, 1.49618, 40.0, 4, SEED, 9)
+    X, V, P, eX, eP, lb = O.pso_variant_iteration(func, LB, UB, o, M, st["X"], st["V"], st["P"], st["eX"],
+                                                  st["eP"], 0, 0, 0.7298, 1.49618, 1.49618, 40.0, 4, SEED, 9)
+    assert np.array_equal(X, ref["X"]) and np.array_equal(V, ref["V"]) and np.array_equal(P, ref["P"])
+    assert np.all(lb == st["g"])
+
+
+def test_pso_ring_neighbourhood_best_brute_force():
+    func, D, np_ = O.RASTRIGIN, 5, 23
+    o, M, st = _swarm(func, D, np_)
+    eP = st["eP"].copy()
+    eP[5] = eP[6] = eP[7] = eP[:].min() - 1.0          # a tie: lowest index wins
+    *_, lb = O.pso_variant_iteration(func, LB, UB, o, M, st["X"], st["V"], st["P"], st["eX"], eP, 1, 0,
+                                     0.7298, 1.49618, 1.49618, 40.0, 4, SEED, 9)
+    for i in range(np_):
+        nb = [(i - 1) % np_, i, (i + 1) % np_]
+        want = min(nb, key=lambda k: (eP[k], k))
+        assert lb[i] == want
+    assert lb[6] == 5 and lb[7] == 6 and lb[5] == 5
+
+
+def test_pso_spherical_sample_in_the_ball_uniformly():
+    """With w = 0, no velocity clamp and a box that never binds, the new
+    position is the sampled point x': it lies in the ball of centre G and
+    radius |G - x|, G from the definition (x, p', l' centroid, or x and p'
+    when the particle is its own neighbourhood best), and (|x' - G| / R)^D is
+    uniform on [0, 1]."""
+    func, D, np_ = O.SCHWEFEL, 6, 40
+    o, M, st = _swarm(func, D, np_)
+    us = []
+    for t in range(10, 40):
+        X, V, P, eX, eP, lb = O.pso_variant_iteration(func, -1e9, 1e9, o, M, st["X"], st["V"], st["P"], st["eX"],
+                                                      st["eP"], 1, 1, 0.0, C_SPSO, C_SPSO, 1e12, 4, SEED, t)
+        x, p = st["X"], st["P"]
+        for i in range(np_):
+            pp = x[i] + C_SPSO * (p[i] - x[i])
+            if lb[i] == i:
+                G = (x[i] + pp) / 2
+            else:
+                G = (x[i] + pp + x[i] + C_SPSO * (p[lb[i]] - x[i])) / 3
+            R = np.linalg.norm(G - x[i])
+            d = np.linalg.norm(X[i] - G)
+            assert d <= R * (1 + 1e-12) + 1e-12
+            if R > 0:
+                us.append((d / R) ** D)
+            else:                  # on its own best: the ball is the point G = x
+                assert d == 0
+    assert len(us) > 900
+    assert stats.kstest(us, "uniform").pvalue > 1e-3
+
+
+def test_pso_variant_runs_fe_accounting():
+    for topo, vel in ((1, 0), (0, 1), (1, 1)):
+        d = _desc(O.ALGO_PSO, O.SPHERE if hasattr(O, "SPHERE") else O.ELLIPSOID, 10, 40, 40 * 101,
+                  topology=topo, velocity=vel, w=W_SPSO if vel else 0.7298,
+                  c1=C_SPSO if vel else 1.49618, c2=C_SPSO if vel else 1.49618)
+        res, trace, _ = O.run(d, SEED, ISEED, trace_len=30)
+        assert res["fes"] == 40 * 101 and res["generations"] == 100
+        assert np.all(np.diff(trace[: res["fes"] // 200]) <= 0) and np.isfinite(res["best_e"])
