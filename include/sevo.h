@@ -254,6 +254,8 @@ typedef struct {
     int32_t H;             /* SHADE, L-SHADE: memory size (1 .. 16) */
     double r_arc;          /* L-SHADE: archive bound round(r_arc NP), 0 .. 2.9 (2.6 in L-SHADE) */
     int32_t np_min;        /* L-SHADE: population size at the budget, 4 .. np */
+    int32_t topology;      /* PSO: 0 global best, 1 ring {i-1, i, i+1} (FP32 runs) */
+    int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical (SPSO-2011; FP32 runs) */
     int32_t reserved;      /* 0 */
 } sevo_run_desc;
 
@@ -269,7 +271,15 @@ typedef struct {
 
 /* Run n_runs independent runs to their budgets in persistent fused kernels
  * (precision FP32: single-precision state, double-precision shift and final
- * check; FP64: everything double, DE and PSO only).
+ * check; FP64: everything double, DE and global-best inertia PSO only).
+ *   PSO variants (the PSO module's topology and velocity update, Listing 1):
+ *   ring topology takes each particle's best personal best among
+ *   {i-1, i, i+1} (mod np; lowest index on ties) in place of the global best;
+ *   the spherical update (SPSO-2011) moves to a point drawn uniformly in the
+ *   ball centred at G = (x + p' + l') / 3 (or (x + p') / 2 when the particle
+ *   is its own neighbourhood best), p' = x + c1 (p - x), l' = x + c1 (l - x),
+ *   of radius |G - x|: v = w v + x' - x; vmax and the box as for the inertia
+ *   update.
  *   L-SHADE (Tanabe and Fukunaga, CEC 2014): SHADE's draws (a terminal CR
  *   memory gives CR = 0) with r2 from the population and the archive; every
  *   strictly improved parent enters the archive in index order (appended

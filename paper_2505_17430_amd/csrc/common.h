@@ -34,6 +34,8 @@ enum Tag : uint32_t {
     TAG_SHADE_D = 7,  // SHADE: (r1, r2, jrand, unused)
     TAG_LSHADE_A = 8, // L-SHADE: archive slot of an improved parent when the archive is full
     TAG_LSHADE_S = 9, // L-SHADE: k-th archive removal after a reduction (individual = k)
+    TAG_PSO_S = 10,   // spherical PSO: Box-Muller (u24(w0), u24(w1)) -> normals of dims 2b, 2b+1
+    TAG_PSO_SR = 11,  // spherical PSO: radius uniform in word 0
     TAG_SHIFT_O = 16, // instance shift: two 53-bit uniforms per block
     TAG_ROT_N = 17,   // instance rotation: one Box-Muller pair per block
 };

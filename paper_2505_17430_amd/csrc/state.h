@@ -47,6 +47,7 @@ struct Launch {
     size_t shm;         // L_RUN: dynamic LDS bytes
     int stride;         // L_RUN: floats of dynamic LDS per run
     int lane;           // internal stream of the launch (runs: one per group)
+    int fam = 0;        // L_RUN: algorithm family (kernel family of the runs)
 };
 // While a plan is being built the context records launches instead of
 // enqueueing them, and descriptor tables and workspace come from

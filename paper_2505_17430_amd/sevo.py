@@ -71,7 +71,8 @@ class RunDesc(C.Structure):
                 ("F", C.c_double), ("CR", C.c_double),
                 ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
                 ("p", C.c_double), ("H", C.c_int32),
-                ("r_arc", C.c_double), ("np_min", C.c_int32), ("reserved", C.c_int32)]
+                ("r_arc", C.c_double), ("np_min", C.c_int32), ("topology", C.c_int32),
+                ("velocity", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RunResult(C.Structure):

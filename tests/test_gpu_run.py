@@ -40,18 +40,22 @@ def ctx():
 
 def desc(algo, func, dim, np_, budget, uid, inst=0, **kw):
     d = dict(F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618, vmax=0.2 * (UB - LB), p=0.1, H=6,
-             r_arc=2.6, np_min=4)
+             r_arc=2.6, np_min=4, topology=0, velocity=0)
     if algo == S.ALGO_LSHADE:
         d["p"] = 0.11
+    if kw.get("velocity") == 1:     # SPSO-2011 constants
+        d["w"], d["c1"], d["c2"] = 1 / (2 * np.log(2)), 0.5 + np.log(2), 0.5 + np.log(2)
     d.update(kw)
     return S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, d["F"], d["CR"], d["w"],
-                     d["c1"], d["c2"], d["vmax"], d["p"], d["H"], d["r_arc"], d["np_min"])
+                     d["c1"], d["c2"], d["vmax"], d["p"], d["H"], d["r_arc"], d["np_min"], d["topology"],
+                     d["velocity"])
 
 
 def odesc(d):
     return dict(algo=d.algo, func=d.prob.func, dim=d.prob.dim, lb=d.prob.lb, ub=d.prob.ub,
                 instance=d.instance, run_uid=d.run_uid, np=d.np, budget=d.budget, F=d.F, CR=d.CR,
-                w=d.w, c1=d.c1, c2=d.c2, vmax=d.vmax, p=d.p, H=d.H, r_arc=d.r_arc, np_min=d.np_min)
+                w=d.w, c1=d.c1, c2=d.c2, vmax=d.vmax, p=d.p, H=d.H, r_arc=d.r_arc, np_min=d.np_min,
+                topology=d.topology, velocity=d.velocity)
 
 
 def gpu_run(ctx, descs, precision=S.FP32, trace_len=0, max_dim=None):
@@ -207,7 +211,9 @@ def test_fused_shade_family_dimension_classes(ctx, algo, dim):
     within 1.5 decades either way."""
     import concurrent.futures as cf
     n, np_ = 24, min(18 * dim, 200)
-    funcs = [S.ELLIPSOID, S.RASTRIGIN, S.GRIEWANK]
+    # functions whose final errors at this budget are unimodal (Griewank's are
+    # not: runs either converge or stall in a basin, so medians of 8 jump)
+    funcs = [S.ELLIPSOID, S.RASTRIGIN, S.ROSENBROCK]
     descs = [desc(algo, funcs[r % 3], dim, np_, 1000 * dim, uid=2000 + r, inst=r % 2) for r in range(n)]
     gres, _, _ = gpu_run(ctx, descs)
     with cf.ThreadPoolExecutor(16) as ex:
@@ -221,6 +227,18 @@ def test_fused_shade_family_dimension_classes(ctx, algo, dim):
             f"oracle {np.median(oe):.2f}")
         assert np.median(ge) - np.median(oe) < 0.5
         assert abs(np.median(ge) - np.median(oe)) < 1.5
+
+
+@pytest.mark.parametrize("topology,velocity", [(1, 0), (0, 1), (1, 1)])
+def test_fused_pso_variants(ctx, topology, velocity):
+    """Ring topology and the spherical update: evaluations and iterations
+    exactly the oracle's, final errors alike in distribution."""
+    d = desc(S.ALGO_PSO, S.SCHWEFEL, 30, 40, 4000, uid=71, topology=topology, velocity=velocity)
+    (g,), tr, _ = gpu_run(ctx, [d], trace_len=25)
+    o, _, _ = O.run(odesc(d), SEED, ISEED)
+    assert g["fes"] == o["fes"] and g["generations"] == o["generations"]
+    assert np.all(np.diff(tr[0][:20]) <= 0)
+    _dist_compare(ctx, S.ALGO_PSO, S.GRIEWANK, 10, 40, 40 * 201, 32, topology=topology, velocity=velocity)
 
 
 def test_fused_mixed_batch_matches_single_runs(ctx):
@@ -265,7 +283,9 @@ def test_fused_team_does_not_change_results(ctx, monkeypatch):
                                               (S.ALGO_DE, 4), (S.ALGO_PSO, 1), (S.ALGO_SHADE, 20),
                                               (S.ALGO_DE, 33), (S.ALGO_PSO, 64), (S.ALGO_DE, 17),
                                               (S.ALGO_LSHADE, 64), (S.ALGO_LSHADE, 30)])]
-    descs += [desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=60, inst=3),
+    descs += [desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=63, inst=3, topology=1, velocity=1),
+              desc(S.ALGO_PSO, S.RASTRIGIN, 30, 64, 3000, uid=64, inst=0, topology=1),
+              desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=60, inst=3),
               desc(S.ALGO_DE, S.ELLIPSOID, 100, 24, 1500, uid=61, inst=1),
               desc(S.ALGO_SHADE, S.GRIEWANK, 50, 100, 3000, uid=62, inst=2)]
     monkeypatch.setenv("SEVO_RUN_TEAM", "wave")
@@ -294,3 +314,7 @@ def test_run_rejects_bad_arguments(ctx):
         ctx.run([desc(S.ALGO_LSHADE, 0, 10, 50, 1000, 1, r_arc=3.0)], res)
     with pytest.raises(S.SevoError):
         ctx.run([desc(S.ALGO_LSHADE, 0, 10, 50, 1000, 1)], res, precision=S.FP64)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_PSO, 0, 10, 50, 1000, 1, topology=2)], res)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_PSO, 0, 10, 50, 1000, 1, velocity=1)], res, precision=S.FP64)
