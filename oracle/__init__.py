@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE = 0, 1, 2, 3
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE = 0, 1, 2, 3, 4
 TRACE_EVERY = 200
 
 
@@ -127,6 +127,10 @@ def lib():
         L.orc_pso_variant_iteration.argtypes = [pp, dp, dp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                                 C.c_double, C.c_double, C.c_double, C.c_uint32, C.c_uint64,
                                                 C.c_uint32, dp, dp, dp, dp, dp, ip]
+        L.orc_psode_generation.argtypes = [pp, dp, dp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                           dp, dp, ip, C.c_uint32, C.c_uint64, C.c_uint32, dp, dp, dp,
+                                           dp, dp, dp, dp, C.POINTER(C.c_uint8)]
         L.orc_run.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
                               dp, C.c_int64, dp]
         for name in ("orc_schwefel_s", "orc_schwefel_c", "orc_schwefel_lambda"):
@@ -362,6 +366,28 @@ def pso_variant_iteration(func, lb, ub, o, M, X, V, P, eX, eP, topology, velocit
     if rc != 0:
         raise ValueError("orc_pso_variant_iteration failed")
     return X, V, P, eX, eP, lbest
+
+
+def psode_generation(func, lb, ub, o, M, X, eX, V, MF, MCR, pos, topology, velocity, w, c1, c2, vmax,
+                     p, run_uid, seed, t):
+    """One PSODE generation (pairwise/3 selection); returns a dict with the
+    new X, eX, V, the PSO moves Y / eY, the DE trials U / eU, the SHADE
+    memory and the choice per individual (0 parent, 1 DE trial, 2 PSO move)."""
+    X, eX, V = (np.ascontiguousarray(a, dtype=np.float64).copy() for a in (X, eX, V))
+    MF = _f64(MF).copy(); MCR = _f64(MCR).copy()
+    posa = np.array([pos], dtype=np.int32)
+    np_, dim = X.shape
+    Y = np.zeros_like(X); eY = np.zeros(np_); U = np.zeros_like(X); eU = np.zeros(np_)
+    choice = np.zeros(np_, dtype=np.uint8)
+    pb = _Problem(func, dim, lb, ub)
+    rc = lib().orc_psode_generation(C.byref(pb), _d(_f64(o)), _d(_f64(M)), np_, topology, velocity,
+                                    w, c1, c2, vmax, p, MF.shape[0], _d(MF), _d(MCR), _p(posa, C.c_int32),
+                                    run_uid, C.c_uint64(seed), t, _d(X), _d(eX), _d(V), _d(Y), _d(eY),
+                                    _d(U), _d(eU), _p(choice, C.c_uint8))
+    if rc != 0:
+        raise ValueError("orc_psode_generation failed")
+    return dict(X=X, eX=eX, V=V, Y=Y, eY=eY, U=U, eU=eU, MF=MF, MCR=MCR, pos=int(posa[0]),
+                choice=choice)
 
 
 def lshade_np(np_init, np_min, budget, fe):

@@ -5,7 +5,9 @@
  *  - The paper's method: modular DE with binomial crossover and the
  *    midpoint-target bound repair, SHADE parameter adaptation with the
  *    current-to-pbest/1 mutation and no external archive (Sec. 2.2,
- *    Listing 1); gbest PSO (Sec. 2.2); whole-generation iteration with
+ *    Listing 1); gbest PSO and the ring / spherical variants (Sec. 2.2,
+ *    Listing 1); L-SHADE (Sec. 2.2, Sec. 4); the PSODE hybrid with
+ *    pairwise/3 selection (Sec. 4, Listing 4); whole-generation iteration with
  *    function-evaluation accounting (Listing 4's loop structure); the
  *    best-so-far recorder every 200 evaluations (Sec. 2.4, Sec. 3.2);
  *    multiple random instances per problem (Sec. 1, Sec. 2.3).
@@ -903,6 +905,53 @@ int orc_lshade_generation(const orc_problem *pb, const double *o, const double *
 }
 
 /* ------------------------------------------------------------------------- */
+/* PSODE (pairwise/3 selection). */
+
+int orc_psode_generation(const orc_problem *pb, const double *o, const double *M, int32_t np,
+                         int32_t topology, int32_t velocity, double w, double c1, double c2,
+                         double vmax, double p, int32_t H, double *MF, double *MCR, int32_t *pos,
+                         uint32_t run_uid, uint64_t seed, uint32_t t, double *X, double *eX, double *V,
+                         double *Y, double *eY, double *U, double *eU, uint8_t *choice)
+{
+    const int D = pb->dim;
+    if (np < 4) return -1;
+    const size_t n = (size_t)np * (size_t)D;
+    double *P = (double *)malloc(sizeof(double) * n);
+    double *X3 = (double *)malloc(sizeof(double) * n);
+    double *eP = (double *)malloc(sizeof(double) * (size_t)np);
+    double *e3 = (double *)malloc(sizeof(double) * (size_t)np);
+    uint8_t *rep = (uint8_t *)malloc((size_t)np);
+    int rc = -1;
+    if (!P || !X3 || !eP || !e3 || !rep) goto done;
+    /* 1. the PSO half moves a copy; the personal bests are the population */
+    memcpy(Y, X, sizeof(double) * n);
+    memcpy(P, X, sizeof(double) * n);
+    memcpy(eP, eX, sizeof(double) * (size_t)np);
+    if (orc_pso_variant_iteration(pb, o, M, np, topology, velocity, w, c1, c2, vmax, run_uid, seed, t,
+                                  Y, V, P, eY, eP, NULL) != 0)
+        goto done;
+    /* 2. the DE half: one SHADE generation with its own greedy selection */
+    if (orc_shade_generation(pb, o, M, np, p, H, MF, MCR, pos, run_uid, seed, t, X, eX, U, eU, X3, e3,
+                             NULL, NULL, NULL, NULL, NULL, rep, NULL) != 0)
+        goto done;
+    for (int i = 0; i < np; ++i) {
+        double *x = X + (size_t)i * D, *v = V + (size_t)i * D;
+        const double *x3 = X3 + (size_t)i * D, *y = Y + (size_t)i * D;
+        /* 3. the velocity becomes the DE displacement */
+        for (int j = 0; j < D; ++j) v[j] = x3[j] - x[j];
+        /* 4. pairwise selection between the PSO move and the DE result */
+        const int pso_wins = key_of(eY[i]) < key_of(e3[i]);
+        memcpy(x, pso_wins ? y : x3, sizeof(double) * (size_t)D);
+        eX[i] = pso_wins ? eY[i] : e3[i];
+        if (choice) choice[i] = (uint8_t)(pso_wins ? 2 : (rep[i] ? 1 : 0));
+    }
+    rc = 0;
+done:
+    free(P); free(X3); free(eP); free(e3); free(rep);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Run driver. */
 
 typedef struct {
@@ -935,7 +984,9 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
 {
     int D = d->dim, np = d->np;
     if (D < 1 || np < 1) return -1;
-    if ((d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE || d->algo == ORC_ALGO_LSHADE) && np < 4) return -1;
+    if ((d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE || d->algo == ORC_ALGO_LSHADE ||
+         d->algo == ORC_ALGO_PSODE) && np < 4)
+        return -1;
     orc_problem pb = { d->func, D, d->lb, d->ub };
     size_t pop = (size_t)np * D;
     double *o = (double *)malloc(sizeof(double) * (size_t)D);
@@ -1022,6 +1073,25 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             for (int i = 0; i < np_old; ++i) record(&rec, eU[i], U + (size_t)i * D);
         }
         free(st.A);
+    } else if (d->algo == ORC_ALGO_PSODE) {
+        double *V = A, *Y = B, *U = C, *eY = eB, *eU = eC;
+        double MF[64], MCR[64];
+        int32_t pos = 0;
+        int H = d->H > 0 ? (d->H > 64 ? 64 : d->H) : 1;
+        for (int k = 0; k < H; ++k) { MF[k] = 0.5; MCR[k] = 0.5; }
+        orc_init_population(&pb, np, d->run_uid, seed, X);
+        orc_error_aos(d->func, D, o, M, X, np, eX);
+        memset(V, 0, sizeof(double) * pop);
+        for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+        while (rec.fe < d->budget) {
+            ++gens;
+            rc = orc_psode_generation(&pb, o, M, np, d->topology, d->velocity, d->w, d->c1, d->c2, d->vmax,
+                                      d->p, H, MF, MCR, &pos, d->run_uid, seed, (uint32_t)gens, X, eX, V,
+                                      Y, eY, U, eU, NULL);
+            if (rc != 0) break;
+            for (int i = 0; i < np; ++i) record(&rec, eY[i], Y + (size_t)i * D);
+            for (int i = 0; i < np; ++i) record(&rec, eU[i], U + (size_t)i * D);
+        }
     } else {
         rc = -1;
     }

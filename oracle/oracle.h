@@ -31,7 +31,7 @@ extern "C" {
 /* Function identifiers (same numbering as the product ABI, by definition). */
 enum { ORC_ELLIPSOID = 0, ORC_ROSENBROCK = 1, ORC_RASTRIGIN = 2,
        ORC_SCHWEFEL = 3, ORC_GRIEWANK = 4, ORC_ACKLEY = 5, ORC_NFUNC = 6 };
-enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3 };
+enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3, ORC_ALGO_PSODE = 4 };
 
 /* Philox stream tags (third counter word, bits 24..31). */
 enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
@@ -184,6 +184,26 @@ int orc_lshade_generation(const orc_problem *pb, const double *o, const double *
 void orc_lshade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos, int32_t n_s,
                               const double *SF, const double *SCR, const double *dS);
 
+/* ---- PSODE: the PSO/DE hybrid with pairwise/3 selection of the case study
+ * (Sec. 4, Listing 4) ----
+ * One generation from the population X / eX and the velocities V:
+ *  1. PSO half: a copy Y of X moves by the PSO module's update
+ *     (orc_pso_variant_iteration with the given topology and velocity
+ *     update; the personal bests are the population itself, since X_i is
+ *     the best point evaluated at index i so far) and is evaluated (eY);
+ *  2. DE half: one SHADE generation from X (orc_shade_generation) gives the
+ *     trials U / eU and the population after its greedy selection, X3 / e3;
+ *  3. V = X3 - X (zero where the trial lost);
+ *  4. X_i = Y_i where e(Y_i) < e3_i (strictly; NaN counts as +infinity),
+ *     else X3_i: the best of parent, DE trial and PSO move.
+ * The two halves draw from disjoint streams (PSO and SHADE tags, counter t).
+ * choice[i] (optional): 0 parent kept, 1 DE trial, 2 PSO move. */
+int orc_psode_generation(const orc_problem *pb, const double *o, const double *M, int32_t np,
+                         int32_t topology, int32_t velocity, double w, double c1, double c2,
+                         double vmax, double p, int32_t H, double *MF, double *MCR, int32_t *pos,
+                         uint32_t run_uid, uint64_t seed, uint32_t t, double *X, double *eX, double *V,
+                         double *Y, double *eY, double *U, double *eU, uint8_t *choice);
+
 /* ---- Whole-run driver with FE accounting and the 200-FE recorder ---- */
 typedef struct {
     int32_t algo;
@@ -202,6 +222,9 @@ typedef struct {
     int32_t topology;      /* PSO: 0 global best, 1 ring */
     int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical */
 } orc_run_desc;
+/* PSODE runs take the PSO fields (w, c1, c2, vmax, topology, velocity) and
+ * SHADE's (p, H); V starts at zero; a generation makes 2 np evaluations,
+ * recorded as the PSO moves in index order, then the DE trials. */
 
 typedef struct {
     double best_e;         /* best error over the first `budget` evaluations */

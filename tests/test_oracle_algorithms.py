@@ -488,3 +488,119 @@ def test_pso_variant_runs_fe_accounting():
         res, trace, _ = O.run(d, SEED, ISEED, trace_len=30)
         assert res["fes"] == 40 * 101 and res["generations"] == 100
         assert np.all(np.diff(trace[: res["fes"] // 200]) <= 0) and np.isfinite(res["best_e"])
+
+
+# ------------------------------------------------------------------ PSODE (pairwise/3)
+
+def _psode_start(func, D, np_, uid=5):
+    o, M, X, eX = _pop(func, D, np_, run_uid=uid)
+    return o, M, X, eX, np.zeros_like(X)
+
+
+def _key(e):
+    e = np.asarray(e, dtype=np.float64)
+    return np.where(np.isnan(e), np.inf, e)
+
+
+@pytest.mark.parametrize("topology", [0, 1])
+def test_psode_reduces_to_shade_when_the_pso_half_stands_still(topology):
+    """With w = c1 = c2 = 0 the inertia update gives v = 0, so every PSO move
+    is the parent itself, evaluated again; ties go to the DE result, so the
+    population, the SHADE memory and the best so far follow SHADE exactly,
+    at twice the evaluations per generation."""
+    func, D, np_ = O.ROSENBROCK, 6, 24
+    o, M, X, eX, V = _psode_start(func, D, np_)
+    MF = np.full(6, 0.5); MCR = np.full(6, 0.5); pos = 0
+    Xs, eXs, MFs, MCRs, poss = X.copy(), eX.copy(), MF.copy(), MCR.copy(), 0
+    for t in range(1, 8):
+        g = O.psode_generation(func, LB, UB, o, M, X, eX, V, MF, MCR, pos, topology, 0, 0.0, 0.0, 0.0,
+                               40.0, 0.1, 5, SEED, t)
+        s = O.shade_generation(func, LB, UB, o, M, Xs, eXs, MFs, MCRs, poss, 0.1, 5, SEED, t)
+        assert np.array_equal(g["Y"], X) and np.array_equal(g["eY"], eX)
+        assert np.array_equal(g["U"], s["U"]) and np.array_equal(g["eU"], s["eU"])
+        assert np.array_equal(g["X"], s["X"]) and np.array_equal(g["eX"], s["eX"])
+        assert np.array_equal(g["MF"], s["MF"]) and np.array_equal(g["MCR"], s["MCR"]) and g["pos"] == s["pos"]
+        assert np.all(g["choice"] != 2)
+        X, eX, V, MF, MCR, pos = g["X"], g["eX"], g["V"], g["MF"], g["MCR"], g["pos"]
+        Xs, eXs, MFs, MCRs, poss = s["X"], s["eX"], s["MF"], s["MCR"], s["pos"]
+    k = 9
+    d_ps = _desc(O.ALGO_PSODE, func, D, np_, np_ * (1 + 2 * k), w=0.0, c1=0.0, c2=0.0, topology=topology)
+    d_sh = _desc(O.ALGO_SHADE, func, D, np_, np_ * (1 + k))
+    r_ps, _, bx_ps = O.run(d_ps, SEED, ISEED)
+    r_sh, _, bx_sh = O.run(d_sh, SEED, ISEED)
+    assert r_ps["generations"] == r_sh["generations"] == k
+    assert r_ps["fes"] == np_ * (1 + 2 * k) and r_sh["fes"] == np_ * (1 + k)
+    assert r_ps["best_e"] == r_sh["best_e"] and np.array_equal(bx_ps, bx_sh)
+
+
+@pytest.mark.parametrize("topology,velocity", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_psode_generation_pairwise3_invariants(topology, velocity):
+    """Each index keeps the best of parent, DE trial and PSO move (the PSO
+    move only when strictly better); V becomes the DE displacement; in the
+    first generation (V = 0) a particle that is its own neighbourhood best
+    stands still under either update (its pull terms vanish)."""
+    func, D, np_ = O.RASTRIGIN, 9, 30
+    o, M, X, eX, V = _psode_start(func, D, np_)
+    w, c = (W_SPSO, C_SPSO) if velocity else (0.7298, 1.49618)
+    MF = np.full(6, 0.5); MCR = np.full(6, 0.5); pos = 0
+    for t in range(1, 6):
+        g = O.psode_generation(func, LB, UB, o, M, X, eX, V, MF, MCR, pos, topology, velocity, w, c, c,
+                               40.0, 0.1, 5, SEED, t)
+        kx, ku, ky = _key(eX), _key(g["eU"]), _key(g["eY"])
+        rep = ku <= kx
+        e3 = np.where(rep, g["eU"], eX)
+        pso = ky < _key(e3)
+        assert np.array_equal(g["choice"], np.where(pso, 2, np.where(rep, 1, 0)))
+        assert np.array_equal(g["eX"], np.where(pso, g["eY"], e3))
+        assert np.all(_key(g["eX"]) <= np.minimum(np.minimum(kx, ku), ky))
+        want_x = np.where(pso[:, None], g["Y"], np.where(rep[:, None], g["U"], X))
+        assert np.array_equal(g["X"], want_x)
+        assert np.array_equal(g["V"], np.where(rep[:, None], g["U"] - X, 0.0))
+        assert np.all(g["Y"] >= LB) and np.all(g["Y"] <= UB)
+        if t == 1:
+            own = [i for i in range(np_)
+                   if (topology == 0 and i == int(np.argmin(kx))) or
+                   (topology == 1 and min([(i - 1) % np_, i, (i + 1) % np_], key=lambda q: (kx[q], q)) == i)]
+            assert own
+            for i in own:
+                assert np.array_equal(g["Y"][i], X[i]) and g["eY"][i] == eX[i]
+        X, eX, V, MF, MCR, pos = g["X"], g["eX"], g["V"], g["MF"], g["MCR"], g["pos"]
+
+
+@pytest.mark.parametrize("velocity", [0, 1])
+def test_psode_run_matches_generations_and_recorder(velocity):
+    """The run driver records the PSO moves, then the DE trials, of each
+    generation; its best, best point and 200-FE trace are recomputed here
+    from the generations."""
+    func, D, np_, budget = O.GRIEWANK, 5, 20, 1300
+    w, c = (W_SPSO, C_SPSO) if velocity else (0.7298, 1.49618)
+    d = _desc(O.ALGO_PSODE, func, D, np_, budget, topology=1, velocity=velocity, w=w, c1=c, c2=c)
+    res, trace, best_x = O.run(d, SEED, ISEED, trace_len=budget // 200)
+    o, M = O.instance(func, D, 0, ISEED)
+    X = O.init_population(func, D, LB, UB, np_, 1, SEED)
+    eX = O.errors(func, o, M, X)
+    V = np.zeros_like(X)
+    evals = list(zip(eX, X))
+    MF = np.full(6, 0.5); MCR = np.full(6, 0.5); pos = 0
+    t = 0
+    while len(evals) < budget:
+        t += 1
+        g = O.psode_generation(func, LB, UB, o, M, X, eX, V, MF, MCR, pos, 1, velocity, w, c, c,
+                               0.2 * (UB - LB), 0.1, 1, SEED, t)
+        evals += list(zip(g["eY"], g["Y"])) + list(zip(g["eU"], g["U"]))
+        X, eX, V, MF, MCR, pos = g["X"], g["eX"], g["V"], g["MF"], g["MCR"], g["pos"]
+    e = np.array([v for v, _ in evals])
+    assert res["fes"] == len(e) == np_ + 2 * np_ * t and res["generations"] == t
+    assert res["best_e"] == e[:budget].min()
+    assert np.array_equal(best_x, evals[int(np.argmin(e[:budget]))][1])
+    assert np.array_equal(trace, [e[: 200 * (k + 1)].min() for k in range(budget // 200)])
+
+
+def test_psode_case_study_fe_accounting():
+    """The case study's shape: D = 30, 100 individuals, 1000 D evaluations:
+    150 generations of 200 evaluations after the initial 100."""
+    d = _desc(O.ALGO_PSODE, O.ROSENBROCK, 30, 100, 30000, topology=1, velocity=1, w=W_SPSO, c1=C_SPSO,
+              c2=C_SPSO)
+    res, trace, _ = O.run(d, SEED, ISEED, trace_len=150)
+    assert res["generations"] == 150 and res["fes"] == 30100
+    assert np.all(np.isfinite(trace)) and np.all(np.diff(trace) <= 0)
