@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -75,9 +76,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "lshade", "copy"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "psode", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
                          "c4: batched SHADE; c5: D=1000 evaluation; lshade: the c4 runs as L-SHADE; "
+                         "psode: the case study's PSO/DE hybrid, batched; "
                          "copy: 512 MiB device copy "
                          "(calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -252,14 +255,29 @@ def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
     print(json.dumps(out), flush=True)
 
 
+_ALGO_PSODE = 4   # SEVO_ALGO_PSODE
+# SPSO-2011 constants of the spherical update: w = 1 / (2 ln 2), c = 1/2 + ln 2
+W_SPSO, C_SPSO = 1.0 / (2.0 * math.log(2.0)), 0.5 + math.log(2.0)
+
+
+def _pso_settings(spec):
+    """(w, c1, c2, topology, velocity) of a run spec: PSODE runs take the case
+    study's PSO (spherical update, ring topology), the others inertia PSO."""
+    if spec[0] == _ALGO_PSODE:
+        return W_SPSO, C_SPSO, C_SPSO, 1, 1
+    return 0.7298, 1.49618, 1.49618, 0, 0
+
+
 def _run_descs(S, specs):
     """specs: list of (algo, func, dim, np, budget, instance, uid).  L-SHADE
     takes its published settings: p = 0.11, archive 2.6 NP, final NP 4."""
     out = []
-    for (algo, func, dim, np_, budget, inst, uid) in specs:
+    for sp in specs:
+        (algo, func, dim, np_, budget, inst, uid) = sp
         p = 0.11 if algo == S.ALGO_LSHADE else 0.1
-        out.append(S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, 0.7298,
-                             1.49618, 1.49618, 0.2 * (W.UB - W.LB), p, 6, 2.6, 4))
+        w, c1, c2, topo, vel = _pso_settings(sp)
+        out.append(S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, w,
+                             c1, c2, 0.2 * (W.UB - W.LB), p, 6, 2.6, 4, topo, vel))
     return out
 
 
@@ -304,9 +322,10 @@ def _oracle_runs(specs, seconds):
 
     def one(sp):
         d = dict(zip(keys, sp))
-        d.update(lb=W.LB, ub=W.UB, F=0.5, CR=0.9, w=0.7298, c1=1.49618, c2=1.49618,
+        w, c1, c2, topo, vel = _pso_settings(sp)
+        d.update(lb=W.LB, ub=W.UB, F=0.5, CR=0.9, w=w, c1=c1, c2=c2,
                  vmax=0.2 * (W.UB - W.LB), p=0.11 if d["algo"] == O.ALGO_LSHADE else 0.1, H=6,
-                 r_arc=2.6, np_min=4)
+                 r_arc=2.6, np_min=4, topology=topo, velocity=vel)
         return O.run(d, W.BASE_SEED, W.INSTANCE_SEED)[0]["fes"]
 
     t0 = time.perf_counter()
@@ -407,6 +426,23 @@ def run_workload(a):
                             "batched L-SHADE: 2048 runs, D in {10,30,50,100}, NP from min(18 D, 200) "
                             "down to 4, budget 10000 D, p = 0.11, H = 6, archive 2.6 NP") +
                            ", persistent fused kernels replayed from a HIP graph", "evals": ev}, **extra)
+    elif a.workload == "psode":
+        spec = []
+        for r in range(4096):
+            f, d, k, np_ = W.psode_run(r)
+            spec.append((S.ALGO_PSODE, f, d, np_, 1000 * d, k, r))
+        descs = _run_descs(S, spec)
+        ms, rr = _time_runs(ctx, S, torch, descs, S.FP32, steps, warm, graph=True)
+        ev = sum(r.fes for r in rr)
+        be = sorted(r.best_e for r in rr)
+        extra = {"median_best_e": be[len(be) // 2]}
+        if not a.no_cpu:
+            extra["cpu_baseline"] = _oracle_runs(spec[:16], 10)
+        _line(metric, ev / (ms / 1e3), "evals/s", steps, warm, ms,
+              {"workload": "batched PSODE (pairwise/3 selection, the case study's hybrid): 4096 runs, "
+                           "Rosenbrock D=30 x 10 instances, NP=100, budget 1000 D; PSO half spherical "
+                           "update with ring topology, DE half SHADE p = 0.1, H = 6; persistent fused "
+                           "kernels replayed from a HIP graph", "evals": ev}, **extra)
     elif a.workload == "c5":
         out = {}
         for prec, name in ((S.SPLIT_BF16, "split_bf16"), (S.FP32, "fp32")):

@@ -80,7 +80,7 @@ enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFE
  * state and errors are double. */
 enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
 
-enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3 };
+enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3, SEVO_ALGO_PSODE = 4 };
 
 typedef struct sevo_ctx sevo_ctx;   /* opaque, library-owned */
 
@@ -249,13 +249,13 @@ typedef struct {
     int32_t np;            /* population / swarm size */
     int64_t budget;        /* function evaluations; whole generations are run */
     double F, CR;          /* DE */
-    double w, c1, c2, vmax;/* PSO */
-    double p;              /* SHADE, L-SHADE: pbest fraction (top max(2, round(p NP))) */
-    int32_t H;             /* SHADE, L-SHADE: memory size (1 .. 16) */
+    double w, c1, c2, vmax;/* PSO, PSODE */
+    double p;              /* SHADE, L-SHADE, PSODE: pbest fraction (top max(2, round(p NP))) */
+    int32_t H;             /* SHADE, L-SHADE, PSODE: memory size (1 .. 16) */
     double r_arc;          /* L-SHADE: archive bound round(r_arc NP), 0 .. 2.9 (2.6 in L-SHADE) */
     int32_t np_min;        /* L-SHADE: population size at the budget, 4 .. np */
-    int32_t topology;      /* PSO: 0 global best, 1 ring {i-1, i, i+1} (FP32 runs) */
-    int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical (SPSO-2011; FP32 runs) */
+    int32_t topology;      /* PSO, PSODE: 0 global best, 1 ring {i-1, i, i+1} (FP32 runs) */
+    int32_t velocity;      /* PSO, PSODE: 0 inertia weight, 1 spherical (SPSO-2011; FP32 runs) */
     int32_t reserved;      /* 0 */
 } sevo_run_desc;
 
@@ -288,6 +288,15 @@ typedef struct {
  *   successful CR are 0; after each generation the population shrinks to
  *   round((np_min - np) FE / budget + np) by dropping the worst (the rest keep
  *   their order) and the archive to its new bound by random removals.
+ *   PSODE (the PSO/DE hybrid with pairwise/3 selection, Sec. 4, Listing 4;
+ *   FP32 runs, np >= 4): each generation moves a copy of the population by
+ *   the PSO update above (topology, velocity; the population serves as the
+ *   personal bests) and evaluates it, runs one SHADE generation on the
+ *   population, sets the velocities to the DE displacement (trial minus
+ *   parent where the trial won, else 0) and keeps per individual the PSO
+ *   move where strictly better than the DE result.  2 np evaluations per
+ *   generation, recorded as the PSO moves, then the DE trials; velocities
+ *   start at 0.
  *   results  device, [n_runs] sevo_run_result.
  *   trace    optional device [n_runs][trace_len] float: best error after
  *            200 (k+1) evaluations, NaN where the run made fewer.

@@ -53,16 +53,17 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
         if (p.func < 0 || p.func >= NFUNC || p.dim < 2 || p.dim > MAX_DIM || !(p.lb < p.ub))
             return set_error(ctx, SEVO_EINVAL, "run has an invalid problem");
         if (d.algo != SEVO_ALGO_DE && d.algo != SEVO_ALGO_PSO && d.algo != SEVO_ALGO_SHADE &&
-            d.algo != SEVO_ALGO_LSHADE)
+            d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_PSODE)
             return set_error(ctx, SEVO_EINVAL, "unknown algorithm");
+        const bool pso_like = d.algo == SEVO_ALGO_PSO || d.algo == SEVO_ALGO_PSODE;
         const int min_np = d.algo == SEVO_ALGO_PSO ? 1 : 4;
         if (d.np < min_np || d.np > RUN_MAX_NP) return set_error(ctx, SEVO_EINVAL, "np outside [4 (1 for PSO), 256]");
         if (d.budget < 1) return set_error(ctx, SEVO_EINVAL, "budget < 1");
         if (d.algo == SEVO_ALGO_DE && (!std::isfinite(d.F) || !(d.CR >= 0 && d.CR <= 1)))
             return set_error(ctx, SEVO_EINVAL, "DE needs finite F and CR in [0, 1]");
-        if (d.algo == SEVO_ALGO_PSO && !(d.vmax > 0))
+        if (pso_like && !(d.vmax > 0))
             return set_error(ctx, SEVO_EINVAL, "PSO needs vmax > 0");
-        if ((d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE) &&
+        if ((d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE || d.algo == SEVO_ALGO_PSODE) &&
             (d.H < 1 || d.H > 16 || !(d.p > 0 && d.p <= 1)))
             return set_error(ctx, SEVO_EINVAL, "SHADE needs H in [1, 16] and p in (0, 1]");
         if (d.algo == SEVO_ALGO_LSHADE && (d.np_min < 4 || d.np_min > d.np || !(d.r_arc >= 0 && d.r_arc <= 2.9)))
@@ -70,11 +71,12 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
         if (best_x && max_dim < p.dim) return set_error(ctx, SEVO_EINVAL, "max_dim < dim");
         if (precision == SEVO_FP32 && p.dim > SMALL_D_MAX)
             return set_error(ctx, SEVO_EUNSUPPORTED, "fused runs support D <= 120");
-        if (d.algo == SEVO_ALGO_PSO && (d.topology < 0 || d.topology > 1 || d.velocity < 0 || d.velocity > 1))
+        if (pso_like && (d.topology < 0 || d.topology > 1 || d.velocity < 0 || d.velocity > 1))
             return set_error(ctx, SEVO_EINVAL, "PSO topology and velocity are 0 or 1");
         if (precision == SEVO_FP64 && d.algo == SEVO_ALGO_PSO && (d.topology != 0 || d.velocity != 0))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision PSO is global-best inertia");
-        if (precision == SEVO_FP64 && (d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE))
+        if (precision == SEVO_FP64 &&
+            (d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE || d.algo == SEVO_ALGO_PSODE))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision run path has DE and PSO");
     }
     return SEVO_OK;
@@ -139,7 +141,7 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
     for (int r = 0; r < n; ++r) {
         const int npp = (runs[r].np + 15) & ~15;
         const size_t D = runs[r].prob.dim;
-        const size_t nbuf = runs[r].algo == SEVO_ALGO_PSO ? 3 : 2;
+        const size_t nbuf = runs[r].algo == SEVO_ALGO_PSODE ? 4 : runs[r].algo == SEVO_ALGO_PSO ? 3 : 2;
         const bool many = small_in_class[ks_of((int)D)] >= 4 * cus;
         wave[r] = !force_block && runs[r].np <= 64 && (many || force_wave) ? 1 : 0;
         dyn[r] = nbuf * D * npp;   // floats
@@ -171,7 +173,7 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.npp = (d.np + 15) & ~15;
         R.run_uid = d.run_uid;
         R.H = d.H;
-        R.pnum = d.algo == SEVO_ALGO_SHADE ? shade_pnum(d.p, d.np) : 0;
+        R.pnum = d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_PSODE ? shade_pnum(d.p, d.np) : 0;
         R.budget = d.budget;
         R.F = (float)d.F;
         R.w = (float)d.w;
@@ -194,8 +196,9 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
             R.X = b; R.U = b + DN; R.V = b + 2 * DN; R.P = b + 3 * DN;
             R.bestx = b + 4 * DN;
         }
-        R.topology = d.algo == SEVO_ALGO_PSO ? d.topology : 0;
-        R.velocity = d.algo == SEVO_ALGO_PSO ? d.velocity : 0;
+        const bool pso_like = d.algo == SEVO_ALGO_PSO || d.algo == SEVO_ALGO_PSODE;
+        R.topology = pso_like ? d.topology : 0;
+        R.velocity = pso_like ? d.velocity : 0;
         R.p = d.p;
         R.r_arc = d.r_arc;
         R.np_min = d.np_min;

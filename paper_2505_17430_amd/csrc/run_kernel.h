@@ -1,6 +1,7 @@
 // run_kernel.h -- whole runs in persistent fused generation kernels (the
 // device code; instantiated per algorithm family in run_de.hip,
-// run_shade.hip, run_lshade.hip and run_pso.hip, launched by run.hip).
+// run_shade.hip, run_lshade.hip, run_pso.hip and run_psode.hip, launched by
+// run.hip).
 //
 // One workgroup (4 waves) carries one run from initialisation to its budget
 // without returning to the host: every generation is variation, the MFMA
@@ -241,13 +242,15 @@ __device__ __forceinline__ void eval_pop(const Team<WAVE> &t, const RunDev &R, i
     }
 }
 
-// Spherical PSO update (SPSO-2011) of the team's np particles.  li[i] is particle i's neighbourhood best (ring) or the
+// Spherical PSO update (SPSO-2011) of the team's np particles, from the
+// positions X to Y (the same array for an update in place).  li[i] is particle i's neighbourhood best (ring) or the
 // global best g; sc and part are team scratch in LDS.  Pass 1 sums, per
 // particle, |G - x|^2 and |z|^2 over each wave's coordinate blocks (waves in
 // order); pass 2 moves to x' = G + r z / |z| with r = |G - x| u^(1/D).
 template <bool WAVE>
 __device__ __forceinline__ void spherical_update(const Team<WAVE> &t, const RunDev &R, uint32_t seed32,
-                                                           uint32_t tg, int np, bool ring, int g, float *X, float *V,
+                                                           uint32_t tg, int np, bool ring, int g, const float *X,
+                                                           float *Y, float *V,
                                                            const float *P, const int *li_arr, float *sc,
                                                            float *part)
 {
@@ -327,7 +330,7 @@ __device__ __forceinline__ void spherical_update(const Team<WAVE> &t, const RunD
                     float xn = xj + vj;
                     if (xn < R.lb) { xn = R.lb; vj = 0.f; }
                     else if (xn > R.ub) { xn = R.ub; vj = 0.f; }
-                    X[row + i] = xn;
+                    Y[row + i] = xn;
                     V[row + i] = vj;
                 }
             }
@@ -370,12 +373,13 @@ __device__ __forceinline__ double check_f64(const Team<WAVE> &t, const RunDev &R
 // in the library workspace.
 // Algorithm families, one kernel each, so that a kernel holds only its own
 // algorithm's paths and registers.
-enum { FAM_DE = 0, FAM_SHADE = 1, FAM_LSHADE = 2, FAM_PSO = 3, NFAM = 4 };
+enum { FAM_DE = 0, FAM_SHADE = 1, FAM_LSHADE = 2, FAM_PSO = 3, FAM_PSODE = 4, NFAM = 5 };
 inline int family_of(int algo)
 {
     return algo == SEVO_ALGO_PSO ? FAM_PSO
          : algo == SEVO_ALGO_SHADE ? FAM_SHADE
          : algo == SEVO_ALGO_LSHADE ? FAM_LSHADE
+         : algo == SEVO_ALGO_PSODE ? FAM_PSODE
                                     : FAM_DE;
 }
 
@@ -433,18 +437,26 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     // the host launches each family's runs apart
     constexpr bool pso = FAM == FAM_PSO;
     constexpr bool lshade = FAM == FAM_LSHADE;
-    constexpr bool shade = FAM == FAM_SHADE || lshade;
-    float *X, *U, *V, *P;
+    // PSODE: a PSO move and a SHADE generation from the same population,
+    // then the pairwise/3 selection
+    constexpr bool psode = FAM == FAM_PSODE;
+    constexpr bool shade = FAM == FAM_SHADE || lshade || psode;
+    constexpr bool moves = pso || psode;   // makes a PSO move each generation
+    // X population; U DE trials; V velocities; P personal bests (PSODE: the
+    // population itself); Y where the PSO move goes (PSO: in place)
+    float *X, *U, *V, *P, *Y;
     if constexpr (ONCHIP) {
         X = sDyn + (WAVE ? s * dyn_stride : 0);
-        U = X + D * npp;   // PSO keeps its velocities here
-        V = U;
-        P = X + 2 * D * npp;
+        U = X + D * npp;
+        V = psode ? X + 2 * D * npp : U;   // PSO keeps its velocities in U's place
+        P = psode ? X : X + 2 * D * npp;
+        Y = psode ? X + 3 * D * npp : X;
     } else {
         X = R.X;
         U = R.U;
         V = R.V;
-        P = R.P;
+        P = psode ? X : R.P;
+        Y = psode ? R.P : X;
     }
     unsigned long long *sKey = sKeyA + base;
     int *sRank = sRankA + base, *sPi = sPiA + base;
@@ -478,6 +490,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                     const float x = (float)((double)R.lb + ((double)R.ub - (double)R.lb) * u24d(word(w, e)));
                     X[j * npp + i] = x;
                     if (pso) { V[j * npp + i] = 0.f; P[j * npp + i] = x; }
+                    if (psode) V[j * npp + i] = 0.f;
                 }
             }
         }
@@ -510,11 +523,11 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
             for (int j = tid; j < D; j += TS) R.bestx[j] = Y[j * npp + cp];
         t.sync();
     };
-    // gbest = argmin e(p), lowest index on ties
-    auto global_best = [&]() {
+    // gbest = argmin of the personal bests' errors e, lowest index on ties
+    auto global_best = [&](const float *e) {
         float pv;
         int pi;
-        prefix_min(t, tid < np ? err_key(sEP[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
+        prefix_min(t, tid < np ? err_key(e[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
         if (tid == 0) sGA[s] = sPi[TS - 1];
         t.sync();
     };
@@ -541,15 +554,20 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     if (pso) {
         if (tid < np) sEP[tid] = sEX[tid];
         t.sync();
-        global_best();
+        global_best(sEP);
     }
+    if (psode && R.topology == 0) global_best(sEX);
     fe = np;
 
     while (fe < R.budget) {
         ++gen;
         const uint32_t tg = (uint32_t)gen;
-        if constexpr (pso) {
+        if constexpr (moves) {
             // ---- PSO: update, evaluate, personal and global bests ----
+            // (PSODE: the move goes to Y, its errors to sEP; the personal
+            // bests are the population)
+            const float *eB = pso ? sEP : sEX;   // errors of the personal bests
+            float *eY = pso ? sEX : sEP;         // errors of the moved particles
             const int g = sGA[s];
             const bool ring = R.topology == 1;
             if (ring) {
@@ -557,11 +575,11 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                 if (tid < np) {
                     const int c0 = (tid + np - 1) % np, c2 = (tid + 1) % np;
                     int best = c0;
-                    float kb = err_key(sEP[c0]);
+                    float kb = err_key(eB[c0]);
                     const int cand[2] = {tid, c2};
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        const float kc = err_key(sEP[cand[q]]);
+                        const float kc = err_key(eB[cand[q]]);
                         if (kc < kb || (kc == kb && cand[q] < best)) { best = cand[q]; kb = kc; }
                     }
                     sDa[tid] = best;
@@ -605,28 +623,33 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                                 float xn = xj[c][e] + vj;
                                 if (xn < R.lb) { xn = R.lb; vj = 0.f; }
                                 else if (xn > R.ub) { xn = R.ub; vj = 0.f; }
-                                X[row + i] = xn;
+                                Y[row + i] = xn;
                                 V[row + i] = vj;
                             }
                         }
                     }
                 }
             } else {
-                spherical_update<WAVE>(t, R, seed32, tg, np, ring, g, X, V, P, sDa, sFi, sPart + WAVE * s * 64);
+                spherical_update<WAVE>(t, R, seed32, tg, np, ring, g, X, Y, V, P, sDa, sFi, sPart + WAVE * s * 64);
             }
             t.sync();
-            eval_pop<KS, ONCHIP>(t, R, np, X, sEX, sA, sO, sT, K);
+            eval_pop<KS, ONCHIP>(t, R, np, Y, eY, sA, sO, sT, K);
             t.sync();
-            record(X, sEX);
-            if (tid < np) {
-                const bool imp = err_key(sEX[tid]) < err_key(sEP[tid]);
-                if (imp) sEP[tid] = sEX[tid];
-                sFlag[tid] = imp ? 1 : 0;
+            record(Y, eY);
+            if constexpr (pso) {
+                if (tid < np) {
+                    const bool imp = err_key(sEX[tid]) < err_key(sEP[tid]);
+                    if (imp) sEP[tid] = sEX[tid];
+                    sFlag[tid] = imp ? 1 : 0;
+                }
+                t.sync();
+                copy_flagged(P, X);
+                global_best(sEP);
+            } else {
+                fe += np;   // the DE half's evaluations follow
             }
-            t.sync();
-            copy_flagged(P, X);
-            global_best();
-        } else {
+        }
+        if constexpr (!pso) {
             // ---- DE rand/1/bin or SHADE current-to-pbest/1 ----
             if (shade) {
                 // ranking by (error, index): every key counts the keys below it
@@ -762,13 +785,48 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                 t.sync();
                 if (tid == 0) sNaA[s] = min(amax, na + total);
             }
-            if (tid < np) {
-                const bool rep = err_key(sEU[tid]) <= err_key(sEX[tid]);
-                if (rep) sEX[tid] = sEU[tid];
-                sFlag[tid] = rep ? 1 : 0;
+            if constexpr (psode) {
+                // pairwise/3: the DE result X3 (the trial where not worse than
+                // its parent), the velocity set to X3 - X, then the PSO move
+                // where strictly better than X3
+                if (tid < np) {
+                    const float kx = err_key(sEX[tid]), ku = err_key(sEU[tid]), ky = err_key(sEP[tid]);
+                    const bool rep = ku <= kx;
+                    const bool pw = ky < (rep ? ku : kx);
+                    sEX[tid] = pw ? sEP[tid] : (rep ? sEU[tid] : sEX[tid]);
+                    sFlag[tid] = (rep ? 1 : 0) | (pw ? 2 : 0);
+                }
+                t.sync();
+                constexpr int SEL_CH = ONCHIP ? 1 : 4;
+                for (int j0 = wave * SEL_CH; j0 < D; j0 += NW * SEL_CH)
+                    for (int i = lane; i < np; i += 64) {
+                        const int f = sFlag[i];
+                        float xv[SEL_CH], uv[SEL_CH], yv[SEL_CH];
+#pragma unroll
+                        for (int c = 0; c < SEL_CH; ++c) {
+                            const int row = min(j0 + c, D - 1) * npp;
+                            xv[c] = X[row + i];
+                            uv[c] = U[row + i];
+                            yv[c] = Y[row + i];
+                        }
+#pragma unroll
+                        for (int c = 0; c < SEL_CH; ++c)
+                            if (j0 + c < D) {
+                                const int row = (j0 + c) * npp;
+                                V[row + i] = (f & 1) ? uv[c] - xv[c] : 0.f;
+                                if (f) X[row + i] = (f & 2) ? yv[c] : uv[c];
+                            }
+                    }
+                t.sync();
+            } else {
+                if (tid < np) {
+                    const bool rep = err_key(sEU[tid]) <= err_key(sEX[tid]);
+                    if (rep) sEX[tid] = sEU[tid];
+                    sFlag[tid] = rep ? 1 : 0;
+                }
+                t.sync();
+                copy_flagged(X, U);
             }
-            t.sync();
-            copy_flagged(X, U);
             if (shade) {
                 team_sums<NSUM>(t, st, sRed);
                 if (tid == 0 && st[5] > 0.0) {
@@ -782,6 +840,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                 }
                 t.sync();
             }
+            if (psode && R.topology == 0) global_best(sEX);
             if (lshade) {
                 // linear population size reduction: the best nn stay, in index order
                 const int nn = min(lshade_np(R.np, R.np_min, R.budget, fe + np), np);
@@ -896,6 +955,7 @@ RunKernel run_table_de(int ks, bool onchip, bool wave);
 RunKernel run_table_shade(int ks, bool onchip, bool wave);
 RunKernel run_table_lshade(int ks, bool onchip, bool wave);
 RunKernel run_table_pso(int ks, bool onchip, bool wave);
+RunKernel run_table_psode(int ks, bool onchip, bool wave);
 inline RunKernel run_table(int fam, int ks, bool onchip, bool wave)
 {
     switch (fam) {
@@ -903,6 +963,7 @@ inline RunKernel run_table(int fam, int ks, bool onchip, bool wave)
     case FAM_SHADE: return run_table_shade(ks, onchip, wave);
     case FAM_LSHADE: return run_table_lshade(ks, onchip, wave);
     case FAM_PSO: return run_table_pso(ks, onchip, wave);
+    case FAM_PSODE: return run_table_psode(ks, onchip, wave);
     default: return nullptr;
     }
 }

@@ -241,6 +241,36 @@ def test_fused_pso_variants(ctx, topology, velocity):
     _dist_compare(ctx, S.ALGO_PSO, S.GRIEWANK, 10, 40, 40 * 201, 32, topology=topology, velocity=velocity)
 
 
+@pytest.mark.parametrize("topology,velocity", [(0, 0), (1, 1)])
+def test_fused_psode(ctx, topology, velocity):
+    """PSODE (pairwise/3): evaluations and generations exactly the oracle's
+    (2 NP per generation), trace monotone, final errors alike in
+    distribution."""
+    d = desc(S.ALGO_PSODE, S.ROSENBROCK, 30, 100, 30000, uid=81, topology=topology, velocity=velocity)
+    (g,), tr, _ = gpu_run(ctx, [d], trace_len=150)
+    o, _, _ = O.run(odesc(d), SEED, ISEED)
+    assert g["fes"] == o["fes"] == 30100 and g["generations"] == o["generations"] == 150
+    assert np.all(np.diff(tr[0]) <= 0)
+    _dist_compare(ctx, S.ALGO_PSODE, S.RASTRIGIN, 10, 40, 40 * 201, 32, topology=topology, velocity=velocity)
+
+
+@pytest.mark.parametrize("topology", [0, 1])
+def test_fused_psode_reduces_to_shade(ctx, topology):
+    """With w = c1 = c2 = 0 the PSO half re-evaluates the parents and ties go
+    to the DE result, so PSODE follows SHADE bit for bit at twice the
+    evaluations: same best, same best point."""
+    k, np_ = 40, 24
+    dp = desc(S.ALGO_PSODE, S.GRIEWANK, 10, np_, np_ * (1 + 2 * k), uid=82, w=0.0, c1=0.0, c2=0.0,
+              topology=topology)
+    ds = desc(S.ALGO_SHADE, S.GRIEWANK, 10, np_, np_ * (1 + k), uid=82)
+    (gp,), _, bp = gpu_run(ctx, [dp])
+    (gs,), _, bs = gpu_run(ctx, [ds])
+    assert gp["generations"] == gs["generations"] == k
+    assert gp["fes"] == np_ * (1 + 2 * k) and gs["fes"] == np_ * (1 + k)
+    assert gp["best_e32"] == gs["best_e32"] and gp["best_e"] == gs["best_e"]
+    assert np.array_equal(bp, bs)
+
+
 def test_fused_mixed_batch_matches_single_runs(ctx):
     """Runs of different algorithms and dimensions in one call give the same
     results as the same runs alone (no cross-run interference)."""
@@ -264,7 +294,9 @@ def test_fused_placement_does_not_change_results(ctx, monkeypatch):
              desc(S.ALGO_SHADE, S.SCHWEFEL, 100, 200, 2000, uid=24),
              desc(S.ALGO_PSO, S.ACKLEY, 10, 7, 500, uid=25),
              desc(S.ALGO_LSHADE, S.RASTRIGIN, 30, 150, 9000, uid=26),
-             desc(S.ALGO_LSHADE, S.GRIEWANK, 100, 200, 6000, uid=27)]
+             desc(S.ALGO_LSHADE, S.GRIEWANK, 100, 200, 6000, uid=27),
+             desc(S.ALGO_PSODE, S.SCHWEFEL, 30, 100, 6000, uid=28, topology=1, velocity=1),
+             desc(S.ALGO_PSODE, S.ELLIPSOID, 100, 60, 3000, uid=29)]
     r1, t1, b1 = gpu_run(ctx, descs, trace_len=30, max_dim=100)
     monkeypatch.setenv("SEVO_RUN_PLACEMENT", "workspace")
     r2, t2, b2 = gpu_run(ctx, descs, trace_len=30, max_dim=100)
@@ -287,7 +319,10 @@ def test_fused_team_does_not_change_results(ctx, monkeypatch):
               desc(S.ALGO_PSO, S.RASTRIGIN, 30, 64, 3000, uid=64, inst=0, topology=1),
               desc(S.ALGO_PSO, S.SCHWEFEL, 10, 40, 3000, uid=60, inst=3),
               desc(S.ALGO_DE, S.ELLIPSOID, 100, 24, 1500, uid=61, inst=1),
-              desc(S.ALGO_SHADE, S.GRIEWANK, 50, 100, 3000, uid=62, inst=2)]
+              desc(S.ALGO_SHADE, S.GRIEWANK, 50, 100, 3000, uid=62, inst=2),
+              desc(S.ALGO_PSODE, S.ACKLEY, 30, 40, 3000, uid=65, topology=1, velocity=1),
+              desc(S.ALGO_PSODE, S.RASTRIGIN, 10, 64, 3000, uid=66, inst=2),
+              desc(S.ALGO_PSODE, S.ROSENBROCK, 50, 17, 3000, uid=67, inst=1, topology=1)]
     monkeypatch.setenv("SEVO_RUN_TEAM", "wave")
     r1, t1, b1 = gpu_run(ctx, descs, trace_len=20, max_dim=100)
     monkeypatch.setenv("SEVO_RUN_TEAM", "block")
@@ -318,3 +353,11 @@ def test_run_rejects_bad_arguments(ctx):
         ctx.run([desc(S.ALGO_PSO, 0, 10, 50, 1000, 1, topology=2)], res)
     with pytest.raises(S.SevoError):
         ctx.run([desc(S.ALGO_PSO, 0, 10, 50, 1000, 1, velocity=1)], res, precision=S.FP64)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_PSODE, 0, 10, 3, 1000, 1)], res)          # NP < 4
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_PSODE, 0, 10, 50, 1000, 1, vmax=0.0)], res)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_PSODE, 0, 10, 50, 1000, 1, H=0)], res)
+    with pytest.raises(S.SevoError):
+        ctx.run([desc(S.ALGO_PSODE, 0, 10, 50, 1000, 1)], res, precision=S.FP64)

@@ -15,6 +15,9 @@ Workloads (synthetic stand-ins: no benchmark-suite data is used):
       function (r div 4) mod 6, instance (r div 24) mod 10, NP = min(18 D, 200),
       budget 10000 D
   C5  large scale: D = 1000, Ellipsoid and Rastrigin, instance 0, 64 runs x 100 points
+  PSODE  the case study's hybrid, batched: 4096 runs, run r -> Rosenbrock, D = 30,
+      instance r mod 10, NP = 100, budget 1000 D; PSO half spherical with ring
+      topology (SPSO-2011 constants), DE half SHADE (p = 0.1, H = 6)
 """
 from __future__ import annotations
 
@@ -68,3 +71,8 @@ def c4_run(r):
     """(func, dim, instance, np) of run r of the batched SHADE workload."""
     d = (10, 30, 50, 100)[r % 4]
     return (r // 4) % 6, d, (r // 24) % 10, min(18 * d, 200)
+
+
+def psode_run(r):
+    """(func, dim, instance, np) of run r of the batched PSODE workload."""
+    return 1, 30, r % 10, 100
