@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE = 0, 1, 2, 3, 4
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO = 0, 1, 2, 3, 4, 5
 TRACE_EVERY = 200
 
 
@@ -131,6 +131,8 @@ def lib():
                                            C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
                                            dp, dp, ip, C.c_uint32, C.c_uint64, C.c_uint32, dp, dp, dp,
                                            dp, dp, dp, dp, C.POINTER(C.c_uint8)]
+        L.orc_cso_iteration.argtypes = [pp, dp, dp, C.c_int32, C.c_double, C.c_uint32, C.c_uint64,
+                                        C.c_uint32, dp, dp, dp, dp, dp, ip, ip]
         L.orc_run.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
                               dp, C.c_int64, dp]
         for name in ("orc_schwefel_s", "orc_schwefel_c", "orc_schwefel_lambda"):
@@ -388,6 +390,21 @@ def psode_generation(func, lb, ub, o, M, X, eX, V, MF, MCR, pos, topology, veloc
         raise ValueError("orc_psode_generation failed")
     return dict(X=X, eX=eX, V=V, Y=Y, eY=eY, U=U, eU=eU, MF=MF, MCR=MCR, pos=int(posa[0]),
                 choice=choice)
+
+
+def cso_iteration(func, lb, ub, o, M, X, V, e, phi, run_uid, seed, t):
+    """One CSO iteration; returns a dict with the new X, V, e, the losers' new
+    positions G / errors eG in pair order and the pairs (winner, loser)."""
+    X, V, e = (np.ascontiguousarray(a, dtype=np.float64).copy() for a in (X, V, e))
+    m, dim = X.shape
+    G = np.zeros((m // 2, dim)); eG = np.zeros(m // 2)
+    win = np.zeros(m // 2, dtype=np.int32); los = np.zeros(m // 2, dtype=np.int32)
+    pb = _Problem(func, dim, lb, ub)
+    rc = lib().orc_cso_iteration(C.byref(pb), _d(_f64(o)), _d(_f64(M)), m, phi, run_uid, C.c_uint64(seed), t,
+                                 _d(X), _d(V), _d(e), _d(G), _d(eG), _p(win, C.c_int32), _p(los, C.c_int32))
+    if rc != 0:
+        raise ValueError("orc_cso_iteration failed")
+    return dict(X=X, V=V, e=e, G=G, eG=eG, winner=win, loser=los)
 
 
 def lshade_np(np_init, np_min, budget, fe):

@@ -7,7 +7,9 @@
  *    current-to-pbest/1 mutation and no external archive (Sec. 2.2,
  *    Listing 1); gbest PSO and the ring / spherical variants (Sec. 2.2,
  *    Listing 1); L-SHADE (Sec. 2.2, Sec. 4); the PSODE hybrid with
- *    pairwise/3 selection (Sec. 4, Listing 4); whole-generation iteration with
+ *    pairwise/3 selection (Sec. 4, Listing 4); the competitive swarm
+ *    optimizer of the large-scale study (Sec. 3.3; Cheng and Jin 2015,
+ *    global-mean variant); whole-generation iteration with
  *    function-evaluation accounting (Listing 4's loop structure); the
  *    best-so-far recorder every 200 evaluations (Sec. 2.4, Sec. 3.2);
  *    multiple random instances per problem (Sec. 1, Sec. 2.3).
@@ -952,6 +954,71 @@ done:
 }
 
 /* ------------------------------------------------------------------------- */
+/* CSO. */
+
+static const uint32_t *g_pair_keys;
+static int cmp_pair(const void *a, const void *b)
+{
+    const int32_t ia = *(const int32_t *)a, ib = *(const int32_t *)b;
+    const uint32_t ka = g_pair_keys[ia], kb = g_pair_keys[ib];
+    if (ka != kb) return ka < kb ? -1 : 1;
+    return ia < ib ? -1 : (ia > ib ? 1 : 0);
+}
+
+int orc_cso_iteration(const orc_problem *pb, const double *o, const double *M, int32_t m, double phi,
+                      uint32_t run_uid, uint64_t seed, uint32_t t, double *X, double *V, double *e,
+                      double *G, double *eG, int32_t *winner, int32_t *loser)
+{
+    const int D = pb->dim;
+    if (m < 2 || m % 2 != 0) return -1;
+    const int h = m / 2;
+    uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)m);
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t *lo = (int32_t *)malloc(sizeof(int32_t) * (size_t)h);
+    double *xbar = (double *)calloc((size_t)D, sizeof(double));
+    if (!keys || !perm || !lo || !xbar) { free(keys); free(perm); free(lo); free(xbar); return -1; }
+    uint32_t w[4];
+    /* random pairing: sort by the drawn key, then by index */
+    for (int i = 0; i < m; ++i) {
+        draw(run_uid, seed, t, (uint32_t)i, ORC_TAG_CSO_PAIR, 0, 0, w);
+        keys[i] = w[0];
+        perm[i] = i;
+    }
+    g_pair_keys = keys;
+    qsort(perm, (size_t)m, sizeof(int32_t), cmp_pair);
+    /* mean position of the swarm before the iteration */
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < D; ++j) xbar[j] += X[(size_t)i * D + j];
+    for (int j = 0; j < D; ++j) xbar[j] /= (double)m;
+    for (int k = 0; k < h; ++k) {
+        const int32_t a = perm[2 * k], b = perm[2 * k + 1];
+        const double ka = key_of(e[a]), kb = key_of(e[b]);
+        const int a_wins = ka < kb || (ka == kb && a < b);
+        const int32_t wi = a_wins ? a : b, li = a_wins ? b : a;
+        if (winner) winner[k] = wi;
+        if (loser) loser[k] = li;
+        lo[k] = li;
+        const double *xw = X + (size_t)wi * D;
+        double *xl = X + (size_t)li * D, *vl = V + (size_t)li * D;
+        for (int j = 0; j < D; ++j) {
+            draw(run_uid, seed, t, (uint32_t)li, ORC_TAG_CSO_R, (uint32_t)j, 0, w);
+            const double r1 = orc_u24(w[0]), r2 = orc_u24(w[1]), r3 = orc_u24(w[2]);
+            double v = r1 * vl[j] + r2 * (xw[j] - xl[j]) + phi * r3 * (xbar[j] - xl[j]);
+            double x = xl[j] + v;
+            if (x < pb->lb) { x = pb->lb; v = 0.0; }
+            else if (x > pb->ub) { x = pb->ub; v = 0.0; }
+            xl[j] = x;
+            vl[j] = v;
+        }
+        memcpy(G + (size_t)k * D, xl, sizeof(double) * (size_t)D);
+    }
+    orc_error_aos(pb->func, D, o, M, G, h, eG);
+    for (int k = 0; k < h; ++k) e[lo[k]] = eG[k];
+    free(keys); free(perm); free(lo); free(xbar);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Run driver. */
 
 typedef struct {
@@ -1091,6 +1158,20 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             if (rc != 0) break;
             for (int i = 0; i < np; ++i) record(&rec, eY[i], Y + (size_t)i * D);
             for (int i = 0; i < np; ++i) record(&rec, eU[i], U + (size_t)i * D);
+        }
+    } else if (d->algo == ORC_ALGO_CSO) {
+        double *V = A, *G = B, *eG = eA;
+        if (np < 2 || np % 2 != 0) { free(o); free(M); free(buf); return -1; }
+        orc_init_population(&pb, np, d->run_uid, seed, X);
+        orc_error_aos(d->func, D, o, M, X, np, eX);
+        memset(V, 0, sizeof(double) * pop);
+        for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+        while (rec.fe < d->budget) {
+            ++gens;
+            rc = orc_cso_iteration(&pb, o, M, np, d->c1, d->run_uid, seed, (uint32_t)gens, X, V, eX, G, eG,
+                                   NULL, NULL);
+            if (rc != 0) break;
+            for (int k = 0; k < np / 2; ++k) record(&rec, eG[k], G + (size_t)k * D);
         }
     } else {
         rc = -1;

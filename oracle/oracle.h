@@ -31,13 +31,14 @@ extern "C" {
 /* Function identifiers (same numbering as the product ABI, by definition). */
 enum { ORC_ELLIPSOID = 0, ORC_ROSENBROCK = 1, ORC_RASTRIGIN = 2,
        ORC_SCHWEFEL = 3, ORC_GRIEWANK = 4, ORC_ACKLEY = 5, ORC_NFUNC = 6 };
-enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3, ORC_ALGO_PSODE = 4 };
+enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3, ORC_ALGO_PSODE = 4,
+       ORC_ALGO_CSO = 5 };
 
 /* Philox stream tags (third counter word, bits 24..31). */
 enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
        ORC_TAG_PSO_R = 4, ORC_TAG_SHADE_P = 5, ORC_TAG_SHADE_C = 6,
        ORC_TAG_SHADE_D = 7, ORC_TAG_LSHADE_A = 8, ORC_TAG_LSHADE_S = 9,
-       ORC_TAG_PSO_S = 10, ORC_TAG_PSO_SR = 11,
+       ORC_TAG_PSO_S = 10, ORC_TAG_PSO_SR = 11, ORC_TAG_CSO_PAIR = 12, ORC_TAG_CSO_R = 13,
        ORC_TAG_SHIFT_O = 16, ORC_TAG_ROT_N = 17 };
 
 typedef struct {
@@ -204,6 +205,27 @@ int orc_psode_generation(const orc_problem *pb, const double *o, const double *M
                          uint32_t run_uid, uint64_t seed, uint32_t t, double *X, double *eX, double *V,
                          double *Y, double *eY, double *U, double *eU, uint8_t *choice);
 
+/* ---- CSO: the competitive swarm optimizer (Cheng and Jin), the optimiser
+ * of the large-scale study (Sec. 3.3: swarm of 300, D = 1000) ----
+ * One iteration on the swarm X / V / e of m particles (m even):
+ *  - pairing: the particles in ascending order of (w_i, i), w_i word 0 of
+ *    the draw (tag CSO_PAIR, counter (t, i)), taken two at a time: pair k is
+ *    (perm[2k], perm[2k+1]);
+ *  - in each pair the particle of lower error wins (NaN counts as +inf; equal
+ *    errors: the lower index wins);
+ *  - the winner passes unchanged; the loser l learns from the winner w:
+ *    v_j = r1 v_j + r2 (x_w,j - x_l,j) + phi r3 (xbar_j - x_l,j), x_l,j += v_j,
+ *    xbar the mean position of the whole swarm before the iteration and
+ *    (r1, r2, r3) the u24 of words 0, 1, 2 of the draw (tag CSO_R, counter
+ *    (t, l), block j); a coordinate leaving the box is put on the bound with
+ *    its velocity zeroed;
+ *  - the losers are evaluated.
+ * G / eG receive the m/2 new loser positions and their errors in pair order;
+ * winner / loser (optional) the pairs. */
+int orc_cso_iteration(const orc_problem *pb, const double *o, const double *M, int32_t m, double phi,
+                      uint32_t run_uid, uint64_t seed, uint32_t t, double *X, double *V, double *e,
+                      double *G, double *eG, int32_t *winner, int32_t *loser);
+
 /* ---- Whole-run driver with FE accounting and the 200-FE recorder ---- */
 typedef struct {
     int32_t algo;
@@ -222,7 +244,9 @@ typedef struct {
     int32_t topology;      /* PSO: 0 global best, 1 ring */
     int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical */
 } orc_run_desc;
-/* PSODE runs take the PSO fields (w, c1, c2, vmax, topology, velocity) and
+/* CSO runs take np = m (even) and phi in c1; V starts at zero; an iteration
+ * makes m/2 evaluations, recorded in pair order.
+ * PSODE runs take the PSO fields (w, c1, c2, vmax, topology, velocity) and
  * SHADE's (p, H); V starts at zero; a generation makes 2 np evaluations,
  * recorded as the PSO moves in index order, then the DE trials. */
 

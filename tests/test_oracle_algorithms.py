@@ -604,3 +604,155 @@ def test_psode_case_study_fe_accounting():
     res, trace, _ = O.run(d, SEED, ISEED, trace_len=150)
     assert res["generations"] == 150 and res["fes"] == 30100
     assert np.all(np.isfinite(trace)) and np.all(np.diff(trace) <= 0)
+
+
+# ------------------------------------------------------------------ CSO (competitive swarm optimizer)
+
+def _fold(seed):
+    return (seed & 0xFFFFFFFF) ^ (seed >> 32)
+
+
+def _cso_start(func, D, m, uid=6):
+    o, M, X, e = _pop(func, D, m, run_uid=uid)
+    return o, M, X, np.zeros_like(X), e
+
+
+def test_cso_pairing_is_the_sorted_key_matching():
+    """Pairs are consecutive entries of the particles sorted by (Philox key,
+    index), recomputed here from the Philox primitive; the lower error wins,
+    the lower index on equal errors; every particle is in exactly one pair."""
+    func, D, m, uid, t = O.ACKLEY, 4, 40, 6, 3
+    o, M, X, V, e = _cso_start(func, D, m, uid)
+    e = e.copy()
+    e[7] = e[11] = e[19] = e[23] = e.min()                      # ties
+    out = O.cso_iteration(func, LB, UB, o, M, X, V, e, 0.1, uid, SEED, t)
+    keys = [int(O.philox([t, i, 12 << 24, 0], [uid, _fold(SEED)])[0]) for i in range(m)]
+    perm = sorted(range(m), key=lambda i: (keys[i], i))
+    for k in range(m // 2):
+        a, b = perm[2 * k], perm[2 * k + 1]
+        a_wins = e[a] < e[b] or (e[a] == e[b] and a < b)
+        assert (out["winner"][k], out["loser"][k]) == ((a, b) if a_wins else (b, a))
+    assert sorted(np.concatenate([out["winner"], out["loser"]])) == list(range(m))
+
+
+def test_cso_iteration_state_invariants():
+    """Winners keep position, velocity and error; each loser takes its new
+    position (kept in the box) and the error of that position."""
+    func, D, m = O.SCHWEFEL, 7, 30
+    o, M, X, V, e = _cso_start(func, D, m)
+    for t in range(1, 5):
+        out = O.cso_iteration(func, LB, UB, o, M, X, V, e, 0.2, 6, SEED, t)
+        w, l = out["winner"], out["loser"]
+        assert np.array_equal(out["X"][w], X[w]) and np.array_equal(out["V"][w], V[w])
+        assert np.array_equal(out["e"][w], e[w])
+        assert np.array_equal(out["X"][l], out["G"]) and np.array_equal(out["e"][l], out["eG"])
+        assert np.all(out["G"] >= LB) and np.all(out["G"] <= UB)
+        assert np.allclose(out["eG"], O.errors(func, o, M, out["G"]), rtol=0, atol=0)
+        X, V, e = out["X"], out["V"], out["e"]
+
+
+def test_cso_first_iteration_moves_along_the_segment_to_the_winner():
+    """With zero velocities and phi = 0 a loser coordinate moves to
+    x_l + r2 (x_w - x_l): the fraction of the way to the winner is uniform
+    on [0, 1)."""
+    func, D, m = O.RASTRIGIN, 20, 200
+    o, M, X, V, e = _cso_start(func, D, m)
+    out = O.cso_iteration(func, -1e9, 1e9, o, M, X, V, e, 0.0, 6, SEED, 1)
+    w, l = out["winner"], out["loser"]
+    frac = ((out["X"][l] - X[l]) / (X[w] - X[l])).ravel()
+    assert np.all(frac >= 0) and np.all(frac < 1)
+    assert stats.kstest(frac, "uniform").pvalue > 1e-3
+    assert np.array_equal(out["V"][l], out["X"][l] - X[l])
+
+
+def test_cso_update_law_by_regression():
+    """Second iteration, phi = 0.3, no clamping: the move y = x' - x_l of a
+    loser coordinate is r1 v + r2 (x_w - x_l) + phi r3 (xbar - x_l) with
+    independent uniforms, so least squares of y on (v, x_w - x_l, xbar - x_l)
+    gives (1/2, 1/2, phi/2); xbar is the mean of the swarm before the move."""
+    func, D, m, phi = O.ELLIPSOID, 50, 300, 0.3
+    o, M, X, V, e = _cso_start(func, D, m)
+    out = O.cso_iteration(func, -1e9, 1e9, o, M, X, V, e, phi, 6, SEED, 1)
+    X, V, e = out["X"], out["V"], out["e"]
+    xbar = X.mean(axis=0)
+    out = O.cso_iteration(func, -1e9, 1e9, o, M, X, V, e, phi, 6, SEED, 2)
+    w, l = out["winner"], out["loser"]
+    y = (out["X"][l] - X[l]).ravel()
+    A = np.stack([V[l].ravel(), (X[w] - X[l]).ravel(), (xbar - X[l]).ravel()], axis=1)
+    coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+    assert np.all(np.abs(coef - [0.5, 0.5, 0.5 * phi]) < [0.03, 0.03, 0.03])
+    # a wrong mean (of the winners only) fits clearly worse
+    xbar_w = X[w].mean(axis=0)
+    A2 = A.copy(); A2[:, 2] = (xbar_w - X[l]).ravel()
+    r1 = np.linalg.lstsq(A, y, rcond=None)[1][0]
+    r2 = np.linalg.lstsq(A2, y, rcond=None)[1][0]
+    assert r1 < r2
+
+
+def test_cso_identical_swarm_is_a_fixed_point():
+    """All particles at one point whose coordinates sum exactly: every pair
+    ties, the pull terms vanish and nothing moves."""
+    func, D, m = O.GRIEWANK, 6, 16
+    o, M = O.instance(func, D, 0, ISEED)
+    X = np.tile(np.array([1.5, -2.25, 0.125, 40.0, -8.5, 3.0]), (m, 1))
+    e = O.errors(func, o, M, X)
+    out = O.cso_iteration(func, LB, UB, o, M, X, np.zeros_like(X), e, 0.1, 6, SEED, 1)
+    assert np.array_equal(out["X"], X) and np.all(out["V"] == 0)
+    assert np.all(out["winner"] < out["loser"])
+
+
+def test_cso_run_matches_iterations_and_recorder():
+    func, D, m, budget = O.ROSENBROCK, 6, 30, 1420
+    d = _desc(O.ALGO_CSO, func, D, m, budget, c1=0.1)
+    res, trace, best_x = O.run(d, SEED, ISEED, trace_len=budget // 200)
+    o, M = O.instance(func, D, 0, ISEED)
+    X = O.init_population(func, D, LB, UB, m, 1, SEED)
+    e = O.errors(func, o, M, X)
+    V = np.zeros_like(X)
+    evals = list(zip(e, X))
+    t = 0
+    while len(evals) < budget:
+        t += 1
+        out = O.cso_iteration(func, LB, UB, o, M, X, V, e, 0.1, 1, SEED, t)
+        evals += list(zip(out["eG"], out["G"]))
+        X, V, e = out["X"], out["V"], out["e"]
+    ev = np.array([v for v, _ in evals])
+    assert res["fes"] == len(ev) == m + (m // 2) * t and res["generations"] == t
+    assert res["best_e"] == ev[:budget].min()
+    assert np.array_equal(best_x, evals[int(np.argmin(ev[:budget]))][1])
+    assert np.array_equal(trace, [ev[: 200 * (k + 1)].min() for k in range(budget // 200)])
+
+
+def test_cso_large_scale_fe_accounting():
+    """The large-scale study's budget: a swarm of 300 and 1e6 evaluations is
+    6665 iterations of 150 after the initial 300 (here at D = 3)."""
+    d = _desc(O.ALGO_CSO, O.ELLIPSOID, 3, 300, 1_000_000, c1=0.1)
+    res, trace, _ = O.run(d, SEED, ISEED, trace_len=5000)
+    assert res["generations"] == 6665 and res["fes"] == 1_000_050
+    assert np.all(np.diff(trace) <= 0)
+
+
+def test_cso_update_draws_are_independent():
+    """The three uniforms of a loser coordinate are independent: the squared
+    residual of the move about its mean has expectation
+    (v^2 + (x_w - x_l)^2 + phi^2 (xbar - x_l)^2) / 12 with no cross terms (a
+    uniform shared by two terms would add 2 phi (x_w - x_l)(xbar - x_l) / 12)."""
+    func, D, m, phi = O.ELLIPSOID, 50, 300, 1.0
+    o, M, X, V, e = _cso_start(func, D, m)
+    rows, ys = [], []
+    for t in (1, 2, 3, 4):
+        xbar = X.mean(axis=0)
+        out = O.cso_iteration(func, -1e9, 1e9, o, M, X, V, e, phi, 6, SEED, t)
+        w, l = out["winner"], out["loser"]
+        if t >= 2:
+            rows.append(np.stack([V[l].ravel(), (X[w] - X[l]).ravel(), (xbar - X[l]).ravel()], axis=1))
+            ys.append((out["X"][l] - X[l]).ravel())
+        X, V, e = out["X"], out["V"], out["e"]
+    A, y = np.concatenate(rows), np.concatenate(ys)
+    res = y - A @ np.array([0.5, 0.5, 0.5 * phi])
+    B = np.stack([A[:, 0] ** 2, A[:, 1] ** 2, A[:, 2] ** 2, A[:, 1] * A[:, 2], A[:, 0] * A[:, 1],
+                  A[:, 0] * A[:, 2]], axis=1)
+    c, *_ = np.linalg.lstsq(B, res ** 2, rcond=None)
+    c = 12 * c
+    assert np.all(np.abs(c[:3] - [1, 1, phi ** 2]) < 0.3)
+    assert np.all(np.abs(c[3:]) < 0.8)
