@@ -77,10 +77,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "psode", "copy"],
+                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "psode", "cso", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
                          "c4: batched SHADE; c5: D=1000 evaluation; lshade: the c4 runs as L-SHADE; "
                          "psode: the case study's PSO/DE hybrid, batched; "
+                         "cso: the large-scale study's CSO runs at D=1000; "
                          "copy: 512 MiB device copy "
                          "(calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -256,15 +257,19 @@ def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
 
 
 _ALGO_PSODE = 4   # SEVO_ALGO_PSODE
+_ALGO_CSO = 5     # SEVO_ALGO_CSO
 # SPSO-2011 constants of the spherical update: w = 1 / (2 ln 2), c = 1/2 + ln 2
 W_SPSO, C_SPSO = 1.0 / (2.0 * math.log(2.0)), 0.5 + math.log(2.0)
 
 
 def _pso_settings(spec):
     """(w, c1, c2, topology, velocity) of a run spec: PSODE runs take the case
-    study's PSO (spherical update, ring topology), the others inertia PSO."""
+    study's PSO (spherical update, ring topology), CSO runs their phi in c1,
+    the others inertia PSO."""
     if spec[0] == _ALGO_PSODE:
         return W_SPSO, C_SPSO, C_SPSO, 1, 1
+    if spec[0] == _ALGO_CSO:
+        return 0.7298, W.CSO_PHI, 1.49618, 0, 0
     return 0.7298, 1.49618, 1.49618, 0, 0
 
 
@@ -443,6 +448,42 @@ def run_workload(a):
                            "Rosenbrock D=30 x 10 instances, NP=100, budget 1000 D; PSO half spherical "
                            "update with ring topology, DE half SHADE p = 0.1, H = 6; persistent fused "
                            "kernels replayed from a HIP graph", "evals": ev}, **extra)
+    elif a.workload == "cso":
+        spec = [W.cso_run(r) for r in range(W.CSO_RUNS)]
+        descs = [S.RunDesc(S.problem(f, d), k, r, S.ALGO_CSO, m, budget, 0.5, 0.9, 0.7298, W.CSO_PHI, 1.49618,
+                           0.2 * (W.UB - W.LB), 0.1, 6, 2.6, 4, 0, 0)
+                 for r, (f, d, k, m, budget) in enumerate(spec)]
+        out = {}
+        for prec, name in ((S.SPLIT_BF16, "split_bf16"), (S.FP32, "fp32")):
+            res = torch.zeros((len(descs), 32), dtype=torch.uint8, device="cuda")
+            st = torch.cuda.current_stream()
+            plan = ctx.plan_run(descs, res, precision=prec)
+            plan.launch(st)                      # warm-up: one whole job
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            plan.launch(st)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            plan.close()
+            raw = res.cpu().numpy().tobytes()
+            rr = [S.RunResult.from_buffer_copy(raw[32 * k: 32 * (k + 1)]) for k in range(len(descs))]
+            ev = sum(r.fes for r in rr)
+            out[name] = {"ms": ms, "evals_per_s": ev / (ms / 1e3),
+                         "median_best_e": sorted(r.best_e for r in rr)[len(rr) // 2]}
+        bf = out["split_bf16"]
+        extra = {"precisions": out}
+        if not a.no_cpu:
+            # whole FP64 runs at D = 1000 take hours: the sample is 16 of the
+            # workload's runs truncated to the initial swarm and 4 iterations
+            short = [(S.ALGO_CSO, f, d, m, m + 4 * (m // 2), k, r) for r, (f, d, k, m, _) in enumerate(spec[:16])]
+            extra["cpu_baseline"] = _oracle_runs(short, 10)
+        _line(metric, bf["evals_per_s"], "evals/s", 1, 1, bf["ms"],
+              {"workload": "large scale: CSO, 30 runs (6 functions x 5 runs) at D=1000, swarm 300, "
+                           "1e6 evaluations each, phi = 0.1; per iteration one update launch and the "
+                           "batched split-bf16 evaluation of all runs' losers", "evals": ev},
+              dtype="bf16x3", **extra)
     elif a.workload == "c5":
         out = {}
         for prec, name in ((S.SPLIT_BF16, "split_bf16"), (S.FP32, "fp32")):

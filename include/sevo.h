@@ -80,7 +80,8 @@ enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFE
  * state and errors are double. */
 enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
 
-enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3, SEVO_ALGO_PSODE = 4 };
+enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3, SEVO_ALGO_PSODE = 4,
+       SEVO_ALGO_CSO = 5 };
 
 typedef struct sevo_ctx sevo_ctx;   /* opaque, library-owned */
 
@@ -246,10 +247,10 @@ typedef struct {
     uint32_t instance;
     uint32_t run_uid;      /* Philox key word 0 of the run */
     int32_t algo;          /* SEVO_ALGO_* */
-    int32_t np;            /* population / swarm size */
+    int32_t np;            /* population / swarm size (CSO: even, 2 .. 1024) */
     int64_t budget;        /* function evaluations; whole generations are run */
     double F, CR;          /* DE */
-    double w, c1, c2, vmax;/* PSO, PSODE */
+    double w, c1, c2, vmax;/* PSO, PSODE; CSO: c1 = phi, the pull towards the swarm mean */
     double p;              /* SHADE, L-SHADE, PSODE: pbest fraction (top max(2, round(p NP))) */
     int32_t H;             /* SHADE, L-SHADE, PSODE: memory size (1 .. 16) */
     double r_arc;          /* L-SHADE: archive bound round(r_arc NP), 0 .. 2.9 (2.6 in L-SHADE) */
@@ -271,7 +272,8 @@ typedef struct {
 
 /* Run n_runs independent runs to their budgets in persistent fused kernels
  * (precision FP32: single-precision state, double-precision shift and final
- * check; FP64: everything double, DE and global-best inertia PSO only).
+ * check; FP64: everything double, DE and global-best inertia PSO only;
+ * SPLIT_BF16: CSO runs only, their evaluation with split-bf16 rotation).
  *   PSO variants (the PSO module's topology and velocity update, Listing 1):
  *   ring topology takes each particle's best personal best among
  *   {i-1, i, i+1} (mod np; lowest index on ties) in place of the global best;
@@ -297,6 +299,14 @@ typedef struct {
  *   move where strictly better than the DE result.  2 np evaluations per
  *   generation, recorded as the PSO moves, then the DE trials; velocities
  *   start at 0.
+ *   CSO (the competitive swarm optimizer of the large-scale study, Sec. 3.3;
+ *   precision FP32 or SPLIT_BF16, any D up to 1024): per iteration the
+ *   swarm is paired at random (ascending Philox key), the lower error of a
+ *   pair wins (ties: lower index), the winner stays and the loser moves by
+ *   v = r1 v + r2 (x_w - x_l) + phi r3 (xbar - x_l), x_l += v (xbar the swarm
+ *   mean, the box as for PSO); the np/2 losers are evaluated (recorded in
+ *   pair order).  Each iteration is an update launch and the batched
+ *   evaluation of all CSO runs' losers; velocities start at 0.
  *   results  device, [n_runs] sevo_run_result.
  *   trace    optional device [n_runs][trace_len] float: best error after
  *            200 (k+1) evaluations, NaN where the run made fewer.

@@ -36,6 +36,8 @@ enum Tag : uint32_t {
     TAG_LSHADE_S = 9, // L-SHADE: k-th archive removal after a reduction (individual = k)
     TAG_PSO_S = 10,   // spherical PSO: Box-Muller (u24(w0), u24(w1)) -> normals of dims 2b, 2b+1
     TAG_PSO_SR = 11,  // spherical PSO: radius uniform in word 0
+    TAG_CSO_PAIR = 12, // CSO: pairing key of particle i in word 0
+    TAG_CSO_R = 13,   // CSO: (r1, r2, r3) of loser l, block = coordinate j
     TAG_SHIFT_O = 16, // instance shift: two 53-bit uniforms per block
     TAG_ROT_N = 17,   // instance rotation: one Box-Muller pair per block
 };

@@ -44,8 +44,8 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
                   const float *trace, const double *best_x, int max_dim)
 {
     if (n < 1 || !runs) return set_error(ctx, SEVO_EINVAL, "no runs");
-    if (precision != SEVO_FP32 && precision != SEVO_FP64)
-        return set_error(ctx, SEVO_EINVAL, "runs take precision FP32 or FP64");
+    if (precision != SEVO_FP32 && precision != SEVO_FP64 && precision != SEVO_SPLIT_BF16)
+        return set_error(ctx, SEVO_EINVAL, "runs take precision FP32, SPLIT_BF16 (CSO) or FP64");
     if (trace_len < 0 || (trace_len > 0 && !trace)) return set_error(ctx, SEVO_EINVAL, "bad trace");
     for (int r = 0; r < n; ++r) {
         const sevo_run_desc &d = runs[r];
@@ -53,8 +53,21 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
         if (p.func < 0 || p.func >= NFUNC || p.dim < 2 || p.dim > MAX_DIM || !(p.lb < p.ub))
             return set_error(ctx, SEVO_EINVAL, "run has an invalid problem");
         if (d.algo != SEVO_ALGO_DE && d.algo != SEVO_ALGO_PSO && d.algo != SEVO_ALGO_SHADE &&
-            d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_PSODE)
+            d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_PSODE && d.algo != SEVO_ALGO_CSO)
             return set_error(ctx, SEVO_EINVAL, "unknown algorithm");
+        if (d.algo == SEVO_ALGO_CSO) {
+            // CSO: the update kernels and the batched evaluation, any D
+            if (d.np < 2 || d.np > 1024 || d.np % 2 != 0)
+                return set_error(ctx, SEVO_EINVAL, "CSO needs an even swarm size in [2, 1024]");
+            if (d.budget < 1) return set_error(ctx, SEVO_EINVAL, "budget < 1");
+            if (!std::isfinite(d.c1)) return set_error(ctx, SEVO_EINVAL, "CSO needs a finite phi (c1)");
+            if (precision == SEVO_FP64)
+                return set_error(ctx, SEVO_EUNSUPPORTED, "CSO runs take precision FP32 or SPLIT_BF16");
+            if (best_x && max_dim < p.dim) return set_error(ctx, SEVO_EINVAL, "max_dim < dim");
+            continue;
+        }
+        if (precision == SEVO_SPLIT_BF16)
+            return set_error(ctx, SEVO_EINVAL, "precision SPLIT_BF16 is for CSO runs only");
         const bool pso_like = d.algo == SEVO_ALGO_PSO || d.algo == SEVO_ALGO_PSODE;
         const int min_np = d.algo == SEVO_ALGO_PSO ? 1 : 4;
         if (d.np < min_np || d.np > RUN_MAX_NP) return set_error(ctx, SEVO_EINVAL, "np outside [4 (1 for PSO), 256]");
@@ -134,11 +147,12 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     std::map<int, int> small_in_class;
     for (int r = 0; r < n; ++r)
-        if (runs[r].np <= 64) ++small_in_class[ks_of(runs[r].prob.dim)];
+        if (runs[r].algo != SEVO_ALGO_CSO && runs[r].np <= 64) ++small_in_class[ks_of(runs[r].prob.dim)];
     std::vector<char> onchip(n), wave(n);
     std::vector<size_t> dyn(n), off(n);
     size_t total = 0;
     for (int r = 0; r < n; ++r) {
+        if (runs[r].algo == SEVO_ALGO_CSO) continue;   // cso.hip runs those
         const int npp = (runs[r].np + 15) & ~15;
         const size_t D = runs[r].prob.dim;
         const size_t nbuf = runs[r].algo == SEVO_ALGO_PSODE ? 4 : runs[r].algo == SEVO_ALGO_PSO ? 3 : 2;
@@ -163,6 +177,7 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
     std::map<int, Group> groups;
     for (int r = 0; r < n; ++r) {
         const sevo_run_desc &d = runs[r];
+        if (d.algo == SEVO_ALGO_CSO) continue;
         InstanceView I;
         if ((rc = lookup_instance(ctx, &d.prob, d.instance, &I))) return rc;
         RunDev R{};
@@ -274,6 +289,18 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
     return recording ? SEVO_OK : join_streams(ctx, stream, ng, ss.data());
 }
 
+// Single-precision runs: the fused kernels for DE, SHADE, L-SHADE, PSO and
+// PSODE, the update-and-evaluate loop for CSO.
+int run_single(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision, sevo_run_result *results,
+               float *trace, int64_t trace_len, double *best_x, int max_dim, hipStream_t stream)
+{
+    bool fused = false;
+    for (int r = 0; r < n; ++r) fused |= runs[r].algo != SEVO_ALGO_CSO;
+    int rc = SEVO_OK;
+    if (fused && (rc = run_fused(ctx, runs, n, results, trace, trace_len, best_x, max_dim, stream))) return rc;
+    return cso_runs(ctx, runs, n, precision, results, trace, trace_len, best_x, max_dim, stream);
+}
+
 }  // namespace
 
 hipError_t sevo::exec_run_launch(const Launch &L, hipStream_t stream, uint32_t seed32, const Consts &k)
@@ -295,14 +322,14 @@ extern "C" int sevo_plan_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n
     if (!results) return set_error(ctx, SEVO_EINVAL, "results is NULL");
     int rc = validate_runs(ctx, runs, n_runs, precision, trace_len, trace, best_x, max_dim);
     if (rc) return rc;
-    if (precision != SEVO_FP32) return set_error(ctx, SEVO_EUNSUPPORTED, "plans run the FP32 fused path only");
+    if (precision == SEVO_FP64) return set_error(ctx, SEVO_EUNSUPPORTED, "plans run single-precision runs only");
     DeviceScope dg(ctx);
     for (int r = 0; r < n_runs; ++r) {   // instances are made before recording
         InstanceView I;
         if ((rc = lookup_instance(ctx, &runs[r].prob, runs[r].instance, &I))) return rc;
     }
     if ((rc = plan_begin(ctx))) return rc;
-    rc = run_fused(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, nullptr);
+    rc = run_single(ctx, runs, n_runs, precision, results, trace, trace_len, best_x, max_dim, nullptr);
     return plan_finish(ctx, rc, out);
 }
 
@@ -315,7 +342,8 @@ extern "C" int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs
     int rc = validate_runs(ctx, runs, n_runs, precision, trace_len, trace, best_x, max_dim);
     if (rc) return rc;
     DeviceScope dg(ctx);
-    if (precision == SEVO_FP32)
-        return run_fused(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, (hipStream_t)stream);
+    if (precision != SEVO_FP64)
+        return run_single(ctx, runs, n_runs, precision, results, trace, trace_len, best_x, max_dim,
+                          (hipStream_t)stream);
     return run_plain_f64(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, (hipStream_t)stream);
 }

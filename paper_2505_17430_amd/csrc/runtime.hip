@@ -346,27 +346,6 @@ int stage_bytes(sevo_ctx *ctx, const std::vector<char> &blob, hipStream_t stream
     return SEVO_OK;
 }
 
-// Stage an evaluation table: item descriptors followed by the logical block
-// -> item map.
-int stage_descs(sevo_ctx *ctx, const std::vector<EvalDesc> &descs, hipStream_t stream,
-                const EvalDesc **d_out, int *slot_out)
-{
-    std::vector<char> blob(descs.size() * sizeof(EvalDesc));
-    std::memcpy(blob.data(), descs.data(), blob.size());
-    int total = 0;
-    for (const auto &d : descs) total = std::max(total, d.block0 + d.nblocks);
-    std::vector<int32_t> map(total, 0);
-    for (size_t i = 0; i < descs.size(); ++i)
-        for (int b = 0; b < descs[i].nblocks; ++b) map[descs[i].block0 + b] = (int32_t)i;
-    const size_t off = blob.size();
-    blob.resize(off + map.size() * sizeof(int32_t));
-    if (!map.empty()) std::memcpy(blob.data() + off, map.data(), map.size() * sizeof(int32_t));
-    const void *d = nullptr;
-    int rc = stage_bytes(ctx, blob, stream, &d, slot_out);
-    *d_out = reinterpret_cast<const EvalDesc *>(d);
-    return rc;
-}
-
 int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
 {
     if (slot < 0) return SEVO_OK;   // plan-owned table
@@ -390,21 +369,41 @@ int small_grid(sevo_ctx *ctx, int ks, int tiles)
 
 }  // namespace
 
-// Evaluate a list of (item, instance) pairs already validated.
-namespace sevo {
-int eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items, int precision,
-               hipStream_t stream);
+// An evaluation table: item descriptors followed by the logical block ->
+// item map.
+static std::vector<char> table_blob(const std::vector<EvalDesc> &descs)
+{
+    std::vector<char> blob(descs.size() * sizeof(EvalDesc));
+    std::memcpy(blob.data(), descs.data(), blob.size());
+    int total = 0;
+    for (const auto &d : descs) total = std::max(total, d.block0 + d.nblocks);
+    std::vector<int32_t> map(total, 0);
+    for (size_t i = 0; i < descs.size(); ++i)
+        for (int b = 0; b < descs[i].nblocks; ++b) map[descs[i].block0 + b] = (int32_t)i;
+    const size_t off = blob.size();
+    blob.resize(off + map.size() * sizeof(int32_t));
+    if (!map.empty()) std::memcpy(blob.data() + off, map.data(), map.size() * sizeof(int32_t));
+    return blob;
 }
 
-int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items,
-                     int precision, hipStream_t stream)
+size_t sevo::large_partial_floats(const std::vector<EvalDesc> &items, int precision)
+{
+    size_t n = 0;
+    for (const auto &d : items)
+        if (precision != SEVO_FP64 && d.n > 0 && d.dim > SMALL_D_MAX)
+            n += (size_t)((d.dim + LARGE_ROWS - 1) / LARGE_ROWS) * d.n * 8;
+    return n;
+}
+
+int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision, float *part,
+                       std::vector<PreparedLaunch> &out)
 {
     // group: FP64 -> one launch; FP32/BF16 small D -> one launch per KS;
-    // large D -> one launch pair.
+    // large D -> one launch pair (partial sums per 128-row block of z, then
+    // a combine pass)
     std::map<int, std::vector<EvalDesc>> small;
     std::vector<EvalDesc> f64, large;
-    for (const auto &pr : items) {
-        const EvalDesc &d = pr.first;
+    for (const auto &d : items) {
         if (d.n <= 0) continue;
         if (precision == SEVO_FP64) f64.push_back(d);
         else if (d.dim <= SMALL_D_MAX) small[ks_of(d.dim)].push_back(d);
@@ -421,14 +420,9 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
             d.nblocks = (d.n + tp - 1) / tp;        // tiles of the item
             tiles += d.nblocks;
         }
-        int grid = small_grid(ctx, ks, tiles);
-        const EvalDesc *dd;
-        int slot;
-        int rc = stage_descs(ctx, v, stream, &dd, &slot);
-        if (rc) return rc;
-        if ((rc = emit_launch(ctx, Launch{L_SMALL, dd, (int)v.size(), ks, tiles, grid, false, false, 0, 0, 0}, stream)))
-            return rc;
-        if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
+        const int grid = small_grid(ctx, ks, tiles);
+        out.push_back({Launch{L_SMALL, nullptr, (int)v.size(), ks, tiles, grid, false, false, 0, 0, 0},
+                       table_blob(v)});
     }
     if (!f64.empty()) {
         int blocks = 0;
@@ -437,60 +431,59 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
             d.nblocks = (d.n + F64_POINTS - 1) / F64_POINTS;
             blocks += d.nblocks;
         }
-        const EvalDesc *dd;
-        int slot;
-        int rc = stage_descs(ctx, f64, stream, &dd, &slot);
-        if (rc) return rc;
-        if ((rc = emit_launch(ctx, Launch{L_F64, dd, (int)f64.size(), 0, blocks, 0, false, false, 0, 0, 0}, stream)))
-            return rc;
-        if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
+        out.push_back({Launch{L_F64, nullptr, (int)f64.size(), 0, blocks, 0, false, false, 0, 0, 0},
+                       table_blob(f64)});
     }
     if (!large.empty()) {
-        int rc = eval_large(ctx, large, precision == SEVO_SPLIT_BF16, stream);
-        if (rc) return rc;
+        if (!part) return set_error(ctx, SEVO_EINVAL, "no partial-sum buffer for a large evaluation");
+        int blocks = 0;
+        size_t off = 0;
+        for (auto &d : large) {
+            d.rb = (d.dim + LARGE_ROWS - 1) / LARGE_ROWS;
+            d.block0 = blocks;
+            d.nblocks = d.rb * ((d.n + LARGE_POINTS - 1) / LARGE_POINTS);
+            blocks += d.nblocks;
+            d.part = part + off;
+            off += (size_t)d.rb * d.n * 8;
+        }
+        out.push_back({Launch{L_LARGE, nullptr, (int)large.size(), 0, blocks, 0, precision == SEVO_SPLIT_BF16,
+                              false, 0, 0, 0},
+                       table_blob(large)});
+        // combine: one thread per point, blocks of 256 points
+        int cblocks = 0;
+        for (auto &d : large) {
+            d.block0 = cblocks;
+            d.nblocks = (d.n + 255) / 256;
+            cblocks += d.nblocks;
+        }
+        out.push_back({Launch{L_COMBINE, nullptr, (int)large.size(), 0, cblocks, 0, false, false, 0, 0, 0},
+                       table_blob(large)});
     }
     return SEVO_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Large-D evaluation: partial sums per 64-row block of z, then a combine pass.
-int sevo::eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStream_t stream)
+// Evaluate a list of (item, instance) pairs already validated: tables staged
+// in the rotating slots, launches enqueued (or recorded by a plan).
+int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items,
+                     int precision, hipStream_t stream)
 {
-    size_t part_elems = 0;
-    int blocks = 0;
-    for (auto &d : v) {
-        d.rb = (d.dim + LARGE_ROWS - 1) / LARGE_ROWS;
-        d.block0 = blocks;
-        d.nblocks = d.rb * ((d.n + LARGE_POINTS - 1) / LARGE_POINTS);
-        blocks += d.nblocks;
-        part_elems += (size_t)d.rb * d.n * 8;
-    }
+    std::vector<EvalDesc> v;
+    v.reserve(items.size());
+    for (const auto &pr : items) v.push_back(pr.first);
     float *part = nullptr;
-    int rc = ctx->ws.get(ctx, WS_PARTIAL, part_elems * sizeof(float), (void **)&part);
-    if (rc) return rc;
-    size_t off = 0;
-    int cblocks = 0;
-    for (auto &d : v) {
-        d.part = part + off;
-        off += (size_t)d.rb * d.n * 8;
+    const size_t pf = large_partial_floats(v, precision);
+    int rc;
+    if (pf && (rc = ctx->ws.get(ctx, WS_PARTIAL, pf * sizeof(float), (void **)&part))) return rc;
+    std::vector<PreparedLaunch> pl;
+    if ((rc = prepare_eval(ctx, std::move(v), precision, part, pl))) return rc;
+    for (auto &p : pl) {
+        const void *d = nullptr;
+        int slot;
+        if ((rc = stage_bytes(ctx, p.table, stream, &d, &slot))) return rc;
+        p.L.d = d;
+        if ((rc = emit_launch(ctx, p.L, stream))) return rc;
+        if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     }
-    const EvalDesc *dd;
-    int slot;
-    if ((rc = stage_descs(ctx, v, stream, &dd, &slot))) return rc;
-    if ((rc = emit_launch(ctx, Launch{L_LARGE, dd, (int)v.size(), 0, blocks, 0, bf16, false, 0, 0, 0}, stream)))
-        return rc;
-    if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
-    // combine: one thread per point, blocks of 256 points
-    std::vector<EvalDesc> c = v;
-    for (auto &d : c) {
-        d.block0 = cblocks;
-        d.nblocks = (d.n + 255) / 256;
-        cblocks += d.nblocks;
-    }
-    if ((rc = stage_descs(ctx, c, stream, &dd, &slot))) return rc;
-    if ((rc = emit_launch(ctx, Launch{L_COMBINE, dd, (int)c.size(), 0, cblocks, 0, false, false, 0, 0, 0}, stream)))
-        return rc;
-    if ((rc = finish_slot_impl(ctx, slot, stream))) return rc;
     return SEVO_OK;
 }
 
@@ -623,6 +616,7 @@ static hipError_t exec_launch(sevo_ctx *ctx, const sevo::Launch &L, hipStream_t 
     case L_LARGE: return launch_eval_large((const EvalDesc *)L.d, L.n, L.total, L.flag, ctx->consts, s);
     case L_COMBINE: return launch_eval_large_combine((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
     case L_RUN: return exec_run_launch(L, s, fold_seed(ctx->base_seed), ctx->consts);
+    case L_CSO: return exec_cso_launch(L, s, fold_seed(ctx->base_seed), ctx->consts);
     default: return hipErrorInvalidValue;
     }
 }

@@ -14,7 +14,7 @@ namespace sevo {
 // Library-owned device scratch, grown on demand and kept until the context
 // is destroyed.  Calls on one context share it, so calls that overlap on
 // different streams must not share a context.
-enum { WS_PARTIAL = 0, WS_STEP = 1, WS_RUN = 2, WS_RUN_DESC = 3, WS_COUNT = 8 };
+enum { WS_PARTIAL = 0, WS_STEP = 1, WS_RUN = 2, WS_RUN_DESC = 3, WS_CSO = 4, WS_COUNT = 8 };
 struct Workspace {
     struct Buf {
         void *ptr = nullptr;
@@ -37,7 +37,7 @@ int set_error(sevo_ctx *ctx, int code, const char *msg);
 
 // One kernel launch of a call, kept by a plan (sevo_plan_*) to be enqueued
 // again later with nothing but launches.
-enum { L_SMALL = 0, L_F64 = 1, L_LARGE = 2, L_COMBINE = 3, L_RUN = 4 };
+enum { L_SMALL = 0, L_F64 = 1, L_LARGE = 2, L_COMBINE = 3, L_RUN = 4, L_CSO = 5 };
 struct Launch {
     int kind;
     const void *d;      // device descriptors
@@ -86,7 +86,21 @@ void release_state(sevo_ctx *ctx);
 
 int eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items, int precision,
                hipStream_t stream);
-int eval_large(sevo_ctx *ctx, std::vector<EvalDesc> &v, bool bf16, hipStream_t stream);
+// The launches of one evaluation with their descriptor tables, not yet
+// staged: L.d is filled in by whoever uploads `table`.  Large-D items take
+// their partial sums from `part` (large_partial_floats floats).
+struct PreparedLaunch {
+    Launch L;
+    std::vector<char> table;
+};
+size_t large_partial_floats(const std::vector<EvalDesc> &items, int precision);
+int prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision, float *part,
+                 std::vector<PreparedLaunch> &out);
+
+// CSO runs (cso.hip): a loop of update kernels and batched evaluations.
+int cso_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision, sevo_run_result *results,
+             float *trace, int64_t trace_len, double *best_x, int max_dim, hipStream_t stream);
+hipError_t exec_cso_launch(const Launch &L, hipStream_t stream, uint32_t seed32, const Consts &k);
 
 // Plain double-precision runs (steps.hip): one run at a time, one launch per
 // generation step.

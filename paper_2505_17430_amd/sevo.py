@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
 FP64, FP32, SPLIT_BF16 = 0, 1, 2
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE = 0, 1, 2, 3, 4
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO = 0, 1, 2, 3, 4, 5
 TRACE_EVERY = 200
 
 

@@ -15,6 +15,8 @@ Workloads (synthetic stand-ins: no benchmark-suite data is used):
       function (r div 4) mod 6, instance (r div 24) mod 10, NP = min(18 D, 200),
       budget 10000 D
   C5  large scale: D = 1000, Ellipsoid and Rastrigin, instance 0, 64 runs x 100 points
+  CSO  the large-scale study's shape: 30 runs, run r -> function r mod 6, D = 1000,
+      instance (r div 6) mod 5, swarm 300, 1e6 evaluations, phi = 0.1
   PSODE  the case study's hybrid, batched: 4096 runs, run r -> Rosenbrock, D = 30,
       instance r mod 10, NP = 100, budget 1000 D; PSO half spherical with ring
       topology (SPSO-2011 constants), DE half SHADE (p = 0.1, H = 6)
@@ -76,3 +78,12 @@ def c4_run(r):
 def psode_run(r):
     """(func, dim, instance, np) of run r of the batched PSODE workload."""
     return 1, 30, r % 10, 100
+
+
+CSO_RUNS = 30
+CSO_PHI = 0.1
+
+
+def cso_run(r):
+    """(func, dim, instance, swarm, budget) of run r of the large-scale CSO workload."""
+    return r % 6, 1000, (r // 6) % 5, 300, 1_000_000
