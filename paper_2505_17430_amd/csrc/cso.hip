@@ -481,12 +481,15 @@ int cso_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision, sev
 
     // evaluation launches, prepared once; one partial-sum buffer serves all
     const size_t pf = std::max(large_partial_floats(init_items, precision), large_partial_floats(g_items[0], precision));
+    const size_t sb = std::max(large_operand_bytes(init_items, precision), large_operand_bytes(g_items[0], precision));
     float *part = nullptr;
+    void *opnd = nullptr;
     if (pf && (rc = ctx_ws(ctx).get(ctx, WS_PARTIAL, pf * sizeof(float), (void **)&part))) return rc;
+    if (sb && (rc = ctx_ws(ctx).get(ctx, WS_OPERANDS, sb, &opnd))) return rc;
     std::vector<PreparedLaunch> ev_init, ev_g[2];
-    if ((rc = prepare_eval(ctx, init_items, precision, part, ev_init))) return rc;
+    if ((rc = prepare_eval(ctx, init_items, precision, part, opnd, ev_init))) return rc;
     for (int p = 0; p < 2; ++p)
-        if ((rc = prepare_eval(ctx, g_items[p], precision, part, ev_g[p]))) return rc;
+        if ((rc = prepare_eval(ctx, g_items[p], precision, part, opnd, ev_g[p]))) return rc;
 
     // one staged blob: the run table, then every evaluation table (256-byte aligned)
     std::vector<char> blob(devs.size() * sizeof(CsoDev));

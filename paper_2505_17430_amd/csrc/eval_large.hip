@@ -1,11 +1,13 @@
 // eval_large.hip -- evaluation of high-dimensional points (D > 120, up to
 // 1024) as a tiled GEMM Z = M * (X - o 1^T) fused with the objective.
 //
-// A workgroup (4 waves) owns a 128-row x 128-point tile of Z.  The K loop
-// stages 32 coordinates of the shifted points in LDS (shift in double, one
-// rounding to float), shared by the 4 waves; each wave streams its own 32
-// rows of M (two 16-row MFMA tiles) from L2 and accumulates 2 x 8 MFMA tiles.
-// Precision variants:
+// A pre-pass (k_eval_operands) makes the shifted points once, in the
+// precision's operand format (shift in double, one rounding to float).  A
+// workgroup (4 waves) owns a 128-row x 128-point tile of Z.  The K loop
+// stages 32 coordinates of its points in LDS, shared by the 4 waves, with
+// the next chunk's loads issued before this chunk's MFMAs; each wave streams
+// its own 32 rows of M (two 16-row MFMA tiles) from L2 and accumulates
+// 2 x 8 MFMA tiles.  Precision variants:
 //   FP32        v_mfma_f32_16x16x4_f32 on float operands;
 //   split bf16  every float is split into hi = bf16(f) and lo = bf16(f - hi);
 //               z += Mhi dhi + Mhi dlo + Mlo dhi on v_mfma_f32_16x16x32_bf16,
@@ -26,6 +28,7 @@ namespace sevo {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t vu32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int xcd_remap_l(int b, int G)
 {
@@ -106,22 +109,89 @@ __device__ __forceinline__ void merge_waves(float rec[4], const float (*sAcc)[PT
     rec[3] = a.c2;
 }
 
+// GEMM operands, made once per point (the row-block workgroups of a point
+// tile would otherwise each redo the shift and the split): d = x - o in
+// double, rounded once to float, zero beyond n and dim.  Workgroup = 64
+// points x 32 coordinates of one item; wave q takes coordinates 8q .. 8q + 7
+// of every point (lanes = points, so the loads of one coordinate are
+// contiguous).  Both layouts are tiled by (128-point tile, 32-coordinate
+// chunk) in the order in which k_eval_large stages one chunk, so that its
+// staging is a contiguous copy:
+//   FP32        [tile][chunk][32 k][128 points] floats; lanes store one
+//               coordinate row of 64 points, 256 contiguous bytes;
+//   split bf16  hi array then lo array, each [tile][chunk][128 points][32 k];
+//               the 8 coordinates of a lane are packed into one 16-byte
+//               vector per array and go through LDS so that the stores of a
+//               wave are 1 KB contiguous.
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_eval_operands(const EvalDesc *__restrict__ items, int n_items,
+                                                       int total_blocks)
+{
+    __shared__ vu32x4 sH[BF16 ? 256 : 1], sL[BF16 ? 256 : 1];
+    const int L = xcd_remap_l(blockIdx.x, total_blocks);
+    const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
+    const int dim = it.dim, n = it.n;
+    const int64_t ld = it.ld, np = large_npad(n), kp = large_kpad(dim);
+    const int local = L - it.block0, pblocks = (int)(np / OPERAND_POINTS);
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int pb = local % pblocks, kc = local / pblocks;
+    const int p = pb * OPERAND_POINTS + lane;
+    const int k0 = kc * OPERAND_K + q * 8;
+    const SEVO_GLOBAL float *__restrict__ X = gin<float>(it.x);
+    const SEVO_GLOBAL double *og = gin<double>(it.o);
+    const int64_t k32 = kp / OPERAND_K;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        const float raw = X[(int64_t)min(k, dim - 1) * ld + min(p, n - 1)];
+        v[e] = (k < dim && p < n) ? (float)((double)raw - og[min(k, dim - 1)]) : 0.f;
+    }
+    if constexpr (!BF16) {
+        // chunk (tile pb / 2, kc) holds 4096 floats; this workgroup's points
+        // are columns 64 (pb & 1) .. + 63 of its 32 rows
+        SEVO_GLOBAL float *D = gout<float>(it.opnd) + ((int64_t)(pb >> 1) * k32 + kc) * 4096 + (pb & 1) * 64 + lane;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) D[(q * 8 + e) * 128] = v[e];
+    } else {
+        uint16_t hi[8], lo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            hi[e] = to_bf16_rne(v[e]);
+            lo[e] = to_bf16_rne(v[e] - from_bf16(hi[e]));
+        }
+        vu32x4 vh, vl;
+        vh.x = hi[0] | ((uint32_t)hi[1] << 16); vh.y = hi[2] | ((uint32_t)hi[3] << 16);
+        vh.z = hi[4] | ((uint32_t)hi[5] << 16); vh.w = hi[6] | ((uint32_t)hi[7] << 16);
+        vl.x = lo[0] | ((uint32_t)lo[1] << 16); vl.y = lo[2] | ((uint32_t)lo[3] << 16);
+        vl.z = lo[4] | ((uint32_t)lo[5] << 16); vl.w = lo[6] | ((uint32_t)lo[7] << 16);
+        sH[lane * 4 + q] = vh;
+        sL[lane * 4 + q] = vl;
+        __syncthreads();
+        // chunk (tile pb / 2, kc) holds 512 vectors; this workgroup's 64
+        // points are its half (pb & 1)
+        const int64_t base = ((int64_t)(pb >> 1) * k32 + kc) * 512 + (pb & 1) * 256;
+        SEVO_GLOBAL vu32x4 *Bh = gout<vu32x4>(it.opnd);
+        SEVO_GLOBAL vu32x4 *Bl = gout<vu32x4>(it.opnd) + np * kp / 8;
+        Bh[base + threadIdx.x] = sH[threadIdx.x];
+        Bl[base + threadIdx.x] = sL[threadIdx.x];
+    }
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__ items, int n_items,
                                                     int total_blocks, Consts K)
 {
-    __shared__ float sB[BF16 ? 1 : KC * SB];
+    __shared__ __attribute__((aligned(16))) float sB[BF16 ? 4 : KC * SB];
     __shared__ __attribute__((aligned(16))) uint16_t sBh[BF16 ? PT * SK : 8];
     __shared__ __attribute__((aligned(16))) uint16_t sBl[BF16 ? PT * SK : 8];
     __shared__ float sZ0[4][PT];
     __shared__ float sZL[PT];
     __shared__ float sAcc[4][PT][4];
-    __shared__ double sO[KC];
 
     const int L = xcd_remap_l(blockIdx.x, total_blocks);
     const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
     const int dim = it.dim, n = it.n, RB = it.rb;
-    const int64_t ld = it.ld;
     const int local = L - it.block0;
     const int rb = local % RB, pb = local / RB;
     const int p_base = pb * PT;
@@ -130,8 +200,6 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
     const int RT = (dim + 15) / 16, KS = (dim + 3) / 4, K32 = (dim + 31) / 32;
     const int rt0 = rb * 8 + w * 2;
     const bool act0 = rt0 < RT, act1 = rt0 + 1 < RT;
-    const SEVO_GLOBAL float *__restrict__ X = gin<float>(it.x);
-    const SEVO_GLOBAL double *og = gin<double>(it.o);
     const SEVO_GLOBAL float *Mf = gin<float>(it.Mfrag);
     const SEVO_GLOBAL float *tab = gin<float>(it.tab);
 
@@ -141,66 +209,151 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
 #pragma unroll
         for (int c = 0; c < CT; ++c) z[rt][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < dim; k0 += KC) {
+    if constexpr (BF16) {
+        // split operands from k_eval_operands: 128 points x 32 coordinates per
+        // chunk and array = 512 vectors of 8 bf16, two per thread; the next
+        // chunk's vectors and M fragments are loaded before this chunk's MFMAs
+        const int64_t kp = large_kpad(dim), np = large_npad(n);
+        // global (not flat) loads: a flat load also counts against the LDS
+        // counter, so the waits for this chunk's LDS reads would wait for the
+        // next chunk's loads as well
+        const SEVO_GLOBAL vu32x4 *Bh = gin<vu32x4>(it.opnd);
+        const SEVO_GLOBAL vu32x4 *Bl = gin<vu32x4>(it.opnd) + np * kp / 8;
+        // tiled layout: chunk kk of this point tile is 512 contiguous vectors
+        const int v0 = threadIdx.x, v1 = threadIdx.x + 256;
+        const int64_t g0 = (int64_t)pb * K32 * 512 + v0, g1 = g0 + 256;
+        const int s0 = (v0 >> 2) * SK + (v0 & 3) * 8, s1 = (v1 >> 2) * SK + (v1 & 3) * 8;
+        const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
+        const int64_t lo_off = (int64_t)RT * K32 * 512;
+        const int rt1 = act1 ? rt0 + 1 : rt0;
+        auto load_a = [&](int kk, bf16x8 &h0, bf16x8 &l0, bf16x8 &h1, bf16x8 &l1) {
+            const int64_t i0 = (((int64_t)min(rt0, RT - 1) * K32 + kk) * 64 + lane) * 8;
+            const int64_t i1 = (((int64_t)min(rt1, RT - 1) * K32 + kk) * 64 + lane) * 8;
+            h0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i0);
+            l0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i0);
+            h1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i1);
+            l1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i1);
+        };
+        // M fragments of row tiles past the matrix are zeroed where they are
+        // loaded, so that the MFMAs run unconditionally (a branch around them
+        // makes the compiler copy the accumulators every iteration) and read
+        // no register whose load may still be in flight at the loop head
+        // (that would make it wait for the prefetch loads in the loop)
+        bf16x8 ah0, al0, ah1, al1;
+        load_a(0, ah0, al0, ah1, al1);
+        if (!act0) { ah0 = bf16x8{}; al0 = bf16x8{}; }
+        if (!act1) { ah1 = bf16x8{}; al1 = bf16x8{}; }
+        vu32x4 bh0 = Bh[g0], bh1 = Bh[g1], bl0 = Bl[g0], bl1 = Bl[g1];
+        *reinterpret_cast<vu32x4 *>(sBh + s0) = bh0;
+        *reinterpret_cast<vu32x4 *>(sBh + s1) = bh1;
+        *reinterpret_cast<vu32x4 *>(sBl + s0) = bl0;
+        *reinterpret_cast<vu32x4 *>(sBl + s1) = bl1;
         __syncthreads();
-        if (threadIdx.x < KC) sO[threadIdx.x] = (k0 + (int)threadIdx.x < dim) ? og[k0 + threadIdx.x] : 0.0;
-        __syncthreads();
-#pragma unroll 4
-        for (int idx = threadIdx.x; idx < KC * PT; idx += 256) {
-            const int kk = idx / PT, p = idx % PT;
-            const int k = k0 + kk, pg = p_base + p;
-            // unconditional load from a clamped address, masked afterwards
-            const float raw = X[(int64_t)min(k, dim - 1) * ld + min(pg, n - 1)];
-            const float v = (k < dim && pg < n) ? (float)((double)raw - sO[kk]) : 0.f;
-            if constexpr (!BF16) {
-                sB[kk * SB + p] = v;
-            } else {
-                const uint16_t hi = to_bf16_rne(v);
-                sBh[p * SK + kk] = hi;
-                sBl[p * SK + kk] = to_bf16_rne(v - from_bf16(hi));
+        for (int kk = 0; kk < K32; ++kk) {
+            const bool more = kk + 1 < K32;
+            bf16x8 nh0, nl0, nh1, nl1;
+            if (more) {
+                const int64_t d = (int64_t)(kk + 1) * 512;
+                bh0 = Bh[g0 + d];
+                bh1 = Bh[g1 + d];
+                bl0 = Bl[g0 + d];
+                bl1 = Bl[g1 + d];
+                load_a(kk + 1, nh0, nl0, nh1, nl1);
             }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int off = (c * 16 + pc) * SK + kq * 8;
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sBh + off);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBl + off);
+                z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, z[0][c], 0, 0, 0);
+                z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, z[0][c], 0, 0, 0);
+                z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, z[0][c], 0, 0, 0);
+                z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z[1][c], 0, 0, 0);
+                z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z[1][c], 0, 0, 0);
+                z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z[1][c], 0, 0, 0);
+            }
+            __syncthreads();
+            if (more) {
+                *reinterpret_cast<vu32x4 *>(sBh + s0) = bh0;
+                *reinterpret_cast<vu32x4 *>(sBh + s1) = bh1;
+                *reinterpret_cast<vu32x4 *>(sBl + s0) = bl0;
+                *reinterpret_cast<vu32x4 *>(sBl + s1) = bl1;
+                ah0 = act0 ? nh0 : bf16x8{};
+                al0 = act0 ? nl0 : bf16x8{};
+                ah1 = act1 ? nh1 : bf16x8{};
+                al1 = act1 ? nl1 : bf16x8{};
+            }
+            __syncthreads();
         }
+    } else {
+        // float operands from k_eval_operands: 32 coordinates x 128 points
+        // per chunk = 1024 vectors of 4 floats, four per thread; the next
+        // chunk's vectors and M fragments are loaded before this chunk's
+        // MFMAs (same structure as the split path)
+        const SEVO_GLOBAL vu32x4 *Bf = gin<vu32x4>(it.opnd);
+        const int64_t g0 = (int64_t)pb * K32 * 1024 + threadIdx.x;
+        // vector v = k (32 vectors per row) and 4 points; LDS row stride SB
+        int sv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = threadIdx.x + 256 * j;
+            sv[j] = (v >> 5) * SB + (v & 31) * 4;
+        }
+        const int rt1 = act1 ? rt0 + 1 : rt0;
+        const int64_t m0 = (int64_t)min(rt0, RT - 1) * KS * 64 + lane;
+        const int64_t m1 = (int64_t)min(rt1, RT - 1) * KS * 64 + lane;
+        // k-steps past the matrix read the last one (their operand rows are
+        // zero); row tiles past the matrix get zero fragments
+        auto load_a = [&](int kk, float (&a0)[KC / 4], float (&a1)[KC / 4]) {
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                const int64_t k = min(kk * (KC / 4) + ks, KS - 1);
+                a0[ks] = Mf[m0 + k * 64];
+                a1[ks] = Mf[m1 + k * 64];
+            }
+        };
+        float a0[KC / 4], a1[KC / 4];
+        load_a(0, a0, a1);
+        vu32x4 b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Bf[g0 + 256 * j];
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            a0[ks] = act0 ? a0[ks] : 0.f;
+            a1[ks] = act1 ? a1[ks] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
         __syncthreads();
-        if (act0) {
-            if constexpr (!BF16) {
+        for (int kk = 0; kk < K32; ++kk) {
+            const bool more = kk + 1 < K32;
+            float n0[KC / 4], n1[KC / 4];
+            if (more) {
+                const int64_t d = (int64_t)(kk + 1) * 1024;
 #pragma unroll
-                for (int ks = 0; ks < KC / 4; ++ks) {
-                    const int ksg = k0 / 4 + ks;
-                    if (ksg < KS) {
-                        const float a0 = Mf[((int64_t)rt0 * KS + ksg) * 64 + lane];
-                        const float a1 = act1 ? Mf[((int64_t)(rt0 + 1) * KS + ksg) * 64 + lane] : 0.f;
+                for (int j = 0; j < 4; ++j) b[j] = Bf[g0 + d + 256 * j];
+                load_a(kk + 1, n0, n1);
+            }
 #pragma unroll
-                        for (int c = 0; c < CT; ++c) {
-                            const float b = sB[(ks * 4 + kq) * SB + c * 16 + pc];
-                            z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, z[0][c], 0, 0, 0);
-                            z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, z[1][c], 0, 0, 0);
-                        }
-                    }
-                }
-            } else {
-                const int kk = k0 / KC;
-                const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
-                const int64_t lo_off = (int64_t)RT * K32 * 512;
-                const int64_t i0 = (((int64_t)rt0 * K32 + kk) * 64 + lane) * 8;
-                const int64_t i1 = (((int64_t)(act1 ? rt0 + 1 : rt0) * K32 + kk) * 64 + lane) * 8;
-                const bf16x8 ah0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i0);
-                const bf16x8 al0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i0);
-                bf16x8 ah1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i1);
-                bf16x8 al1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i1);
-                if (!act1) { ah1 = bf16x8{}; al1 = bf16x8{}; }
+            for (int ks = 0; ks < KC / 4; ++ks) {
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
-                    const int off = (c * 16 + pc) * SK + kq * 8;
-                    const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sBh + off);
-                    const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBl + off);
-                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, z[0][c], 0, 0, 0);
-                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, z[0][c], 0, 0, 0);
-                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, z[0][c], 0, 0, 0);
-                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z[1][c], 0, 0, 0);
-                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z[1][c], 0, 0, 0);
-                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z[1][c], 0, 0, 0);
+                    const float bv = sB[(ks * 4 + kq) * SB + c * 16 + pc];
+                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv, z[0][c], 0, 0, 0);
+                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, z[1][c], 0, 0, 0);
                 }
             }
+            __syncthreads();
+            if (more) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
+#pragma unroll
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    a0[ks] = act0 ? n0[ks] : 0.f;
+                    a1[ks] = act1 ? n1[ks] : 0.f;
+                }
+            }
+            __syncthreads();
         }
     }
 
@@ -294,6 +447,19 @@ hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blo
     else
         hipLaunchKernelGGL(k_eval_large<false>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
                            total_blocks, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_operands(const EvalDesc *d_items, int n_items, int total_blocks, bool split_bf16,
+                               hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    if (split_bf16)
+        hipLaunchKernelGGL(k_eval_operands<true>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
+                           total_blocks);
+    else
+        hipLaunchKernelGGL(k_eval_operands<false>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
+                           total_blocks);
     return hipGetLastError();
 }
 

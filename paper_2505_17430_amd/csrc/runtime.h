@@ -43,6 +43,7 @@ struct EvalDesc {
     const double *M64;      // [dim][dim] row-major
     const uint16_t *Mbf;    // bf16 hi block then lo block, each [RT][KS32][64][8]
     float *part;            // large-D partial sums [RB][n][8] (workspace)
+    void *opnd;             // large-D GEMM operands, 4 npad kpad bytes (workspace; layout at launch_eval_operands)
     int64_t ld;
     int32_t n;
     int32_t func;
@@ -77,6 +78,19 @@ hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blo
                              bool split_bf16, const Consts &k, hipStream_t s);
 hipError_t launch_eval_large_combine(const EvalDesc *d_items, int n_items, int total_blocks,
                                      const Consts &k, hipStream_t s);
+// GEMM operands of the large-D points, made by a pre-pass: d = x - o
+// (double, rounded once to float), zero beyond n and dim, tiled by
+// (128-point tile, 32-coordinate chunk) in the order in which the
+// evaluation stages one chunk:
+//   FP32        [npad / 128][kpad / 32][32 k][128 points] floats;
+//   split bf16  hi = bf16(d), lo = bf16(d - hi): the hi array then the lo
+//               array, each [npad / 128][kpad / 32][128 points][32 k].
+// Either way 4 npad kpad bytes.  Workgroups of 64 points x 32 coordinates.
+constexpr int OPERAND_POINTS = 64, OPERAND_K = 32;
+__host__ __device__ inline int64_t large_npad(int n) { return ((int64_t)n + LARGE_POINTS - 1) / LARGE_POINTS * LARGE_POINTS; }
+__host__ __device__ inline int64_t large_kpad(int dim) { return ((int64_t)dim + 31) / 32 * 32; }
+hipError_t launch_eval_operands(const EvalDesc *d_items, int n_items, int total_blocks, bool split_bf16,
+                               hipStream_t s);
 
 constexpr int F64_POINTS = 64;           // points per workgroup of the double path
 hipError_t launch_eval_f64(const EvalDesc *d_items, int n_items, int total_blocks,

@@ -395,7 +395,16 @@ size_t sevo::large_partial_floats(const std::vector<EvalDesc> &items, int precis
     return n;
 }
 
-int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision, float *part,
+size_t sevo::large_operand_bytes(const std::vector<EvalDesc> &items, int precision)
+{
+    size_t n = 0;
+    if (precision == SEVO_FP64) return 0;
+    for (const auto &d : items)
+        if (d.n > 0 && d.dim > SMALL_D_MAX) n += (size_t)(4 * large_npad(d.n) * large_kpad(d.dim));
+    return n;
+}
+
+int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision, float *part, void *opnd,
                        std::vector<PreparedLaunch> &out)
 {
     // group: FP64 -> one launch; FP32/BF16 small D -> one launch per KS;
@@ -436,6 +445,22 @@ int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision
     }
     if (!large.empty()) {
         if (!part) return set_error(ctx, SEVO_EINVAL, "no partial-sum buffer for a large evaluation");
+        // operands first: blocks of 64 points x 32 coordinates over the
+        // padded tile grid
+        if (!opnd) return set_error(ctx, SEVO_EINVAL, "no operand buffer for a large evaluation");
+        const bool bf16 = precision == SEVO_SPLIT_BF16;
+        int oblocks = 0;
+        size_t ooff = 0;
+        for (auto &d : large) {
+            const int64_t np = large_npad(d.n), kp = large_kpad(d.dim);
+            d.opnd = static_cast<char *>(opnd) + ooff;
+            ooff += (size_t)(4 * np * kp);
+            d.block0 = oblocks;
+            d.nblocks = (int)((np / OPERAND_POINTS) * (kp / OPERAND_K));
+            oblocks += d.nblocks;
+        }
+        out.push_back({Launch{L_OPERANDS, nullptr, (int)large.size(), 0, oblocks, 0, bf16, false, 0, 0, 0},
+                       table_blob(large)});
         int blocks = 0;
         size_t off = 0;
         for (auto &d : large) {
@@ -471,11 +496,13 @@ int sevo::eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> 
     v.reserve(items.size());
     for (const auto &pr : items) v.push_back(pr.first);
     float *part = nullptr;
-    const size_t pf = large_partial_floats(v, precision);
+    const size_t pf = large_partial_floats(v, precision), sb = large_operand_bytes(v, precision);
+    void *opnd = nullptr;
     int rc;
     if (pf && (rc = ctx->ws.get(ctx, WS_PARTIAL, pf * sizeof(float), (void **)&part))) return rc;
+    if (sb && (rc = ctx->ws.get(ctx, WS_OPERANDS, sb, &opnd))) return rc;
     std::vector<PreparedLaunch> pl;
-    if ((rc = prepare_eval(ctx, std::move(v), precision, part, pl))) return rc;
+    if ((rc = prepare_eval(ctx, std::move(v), precision, part, opnd, pl))) return rc;
     for (auto &p : pl) {
         const void *d = nullptr;
         int slot;
@@ -615,6 +642,7 @@ static hipError_t exec_launch(sevo_ctx *ctx, const sevo::Launch &L, hipStream_t 
     case L_F64: return launch_eval_f64((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
     case L_LARGE: return launch_eval_large((const EvalDesc *)L.d, L.n, L.total, L.flag, ctx->consts, s);
     case L_COMBINE: return launch_eval_large_combine((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
+    case L_OPERANDS: return launch_eval_operands((const EvalDesc *)L.d, L.n, L.total, L.flag, s);
     case L_RUN: return exec_run_launch(L, s, fold_seed(ctx->base_seed), ctx->consts);
     case L_CSO: return exec_cso_launch(L, s, fold_seed(ctx->base_seed), ctx->consts);
     default: return hipErrorInvalidValue;

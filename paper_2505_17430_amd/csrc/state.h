@@ -14,7 +14,7 @@ namespace sevo {
 // Library-owned device scratch, grown on demand and kept until the context
 // is destroyed.  Calls on one context share it, so calls that overlap on
 // different streams must not share a context.
-enum { WS_PARTIAL = 0, WS_STEP = 1, WS_RUN = 2, WS_RUN_DESC = 3, WS_CSO = 4, WS_COUNT = 8 };
+enum { WS_PARTIAL = 0, WS_STEP = 1, WS_RUN = 2, WS_RUN_DESC = 3, WS_CSO = 4, WS_OPERANDS = 5, WS_COUNT = 8 };
 struct Workspace {
     struct Buf {
         void *ptr = nullptr;
@@ -37,12 +37,12 @@ int set_error(sevo_ctx *ctx, int code, const char *msg);
 
 // One kernel launch of a call, kept by a plan (sevo_plan_*) to be enqueued
 // again later with nothing but launches.
-enum { L_SMALL = 0, L_F64 = 1, L_LARGE = 2, L_COMBINE = 3, L_RUN = 4, L_CSO = 5 };
+enum { L_SMALL = 0, L_F64 = 1, L_LARGE = 2, L_COMBINE = 3, L_RUN = 4, L_CSO = 5, L_OPERANDS = 6 };
 struct Launch {
     int kind;
     const void *d;      // device descriptors
     int n, ks, total, grid;
-    bool flag;          // L_LARGE: split bf16; L_RUN: population on chip
+    bool flag;          // L_LARGE, L_OPERANDS: split bf16; L_RUN: population on chip
     bool wave;          // L_RUN: wave teams
     size_t shm;         // L_RUN: dynamic LDS bytes
     int stride;         // L_RUN: floats of dynamic LDS per run
@@ -88,13 +88,15 @@ int eval_items(sevo_ctx *ctx, const std::vector<std::pair<EvalDesc, int>> &items
                hipStream_t stream);
 // The launches of one evaluation with their descriptor tables, not yet
 // staged: L.d is filled in by whoever uploads `table`.  Large-D items take
-// their partial sums from `part` (large_partial_floats floats).
+// their partial sums from `part` (large_partial_floats floats) and their
+// GEMM operands from `opnd` (large_operand_bytes bytes).
 struct PreparedLaunch {
     Launch L;
     std::vector<char> table;
 };
 size_t large_partial_floats(const std::vector<EvalDesc> &items, int precision);
-int prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision, float *part,
+size_t large_operand_bytes(const std::vector<EvalDesc> &items, int precision);
+int prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision, float *part, void *opnd,
                  std::vector<PreparedLaunch> &out);
 
 // CSO runs (cso.hip): a loop of update kernels and batched evaluations.
