@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO = 0, 1, 2, 3, 4, 5
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO, ALGO_JADE = 0, 1, 2, 3, 4, 5, 6
 TRACE_EVERY = 200
 
 
@@ -54,6 +54,7 @@ class RunDesc(C.Structure):
         ("p", C.c_double), ("H", C.c_int32),
         ("r_arc", C.c_double), ("np_min", C.c_int32),
         ("topology", C.c_int32), ("velocity", C.c_int32),
+        ("c", C.c_double),
     ]
 
 
@@ -135,6 +136,12 @@ def lib():
                                         C.c_uint32, dp, dp, dp, dp, dp, ip, ip]
         L.orc_run.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
                               dp, C.c_int64, dp]
+        L.orc_run_observed.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
+                                       dp, C.c_int64, dp, dp, C.c_int64]
+        L.orc_jade_update.argtypes = [C.c_double, dp, dp, C.c_int32, dp, dp]
+        L.orc_jade_update.restype = None
+        L.orc_jade_generation.argtypes = [pp, dp, dp, C.POINTER(_LShadeState), C.c_double, C.c_double,
+                                          C.c_double, C.c_uint32, C.c_uint64, C.c_uint32, dp, dp, ip]
         for name in ("orc_schwefel_s", "orc_schwefel_c", "orc_schwefel_lambda"):
             getattr(L, name).restype = C.c_double
             getattr(L, name).argtypes = []
@@ -469,16 +476,48 @@ class LShade:
             raise ValueError("orc_lshade_generation failed")
         return U, eU, int(ns[0])
 
+    def jade_generation(self, p, c, run_uid, seed, t):
+        """JADE's generation (the state must have H = 1); returns (trials U,
+        their errors eU, number of successes)."""
+        n = self.st.np
+        D = self.pb.dim
+        U = np.zeros((n, D))
+        eU = np.zeros(n)
+        ns = np.zeros(1, dtype=np.int32)
+        rc = lib().orc_jade_generation(C.byref(self.pb), _d(self.o), _d(self.M), C.byref(self.st),
+                                      C.c_double(p), C.c_double(self.r_arc), C.c_double(c), run_uid,
+                                      C.c_uint64(seed), t, _d(U), _d(eU), _p(ns, C.c_int32))
+        if rc != 0:
+            raise ValueError("orc_jade_generation failed")
+        return U, eU, int(ns[0])
 
-def run(desc: dict, seed, inst_seed, trace_len=0):
-    """Whole run; returns (result dict, trace array, best x)."""
+
+def run(desc: dict, seed, inst_seed, trace_len=0, mu_len=None):
+    """Whole run; returns (result dict, trace array, best x), and with
+    mu_len also the observer's [mu_len, 2] array of (muF, muCR) after each
+    generation (orc_run_observed)."""
     d = RunDesc(**{k: v for k, v in desc.items()})
     res = RunResult()
     trace = np.full(max(trace_len, 0), np.nan)
     best_x = np.zeros(desc["dim"])
-    rc = lib().orc_run(C.byref(d), seed, inst_seed, C.byref(res),
-                       _d(trace) if trace_len > 0 else None, trace_len, _d(best_x))
+    tr = _d(trace) if trace_len > 0 else None
+    if mu_len is None:
+        rc = lib().orc_run(C.byref(d), seed, inst_seed, C.byref(res), tr, trace_len, _d(best_x))
+    else:
+        mu = np.zeros((max(mu_len, 0), 2))
+        rc = lib().orc_run_observed(C.byref(d), seed, inst_seed, C.byref(res), tr, trace_len, _d(best_x),
+                                    _d(mu) if mu_len > 0 else None, mu_len)
     if rc != 0:
         raise ValueError("orc_run failed")
-    return (dict(best_e=res.best_e, fes=res.fes, generations=res.generations,
-                 success=bool(res.success)), trace, best_x)
+    out = (dict(best_e=res.best_e, fes=res.fes, generations=res.generations,
+                success=bool(res.success)), trace, best_x)
+    return out if mu_len is None else out + (mu,)
+
+
+def jade_update(c, muF, muCR, SF, SCR):
+    """JADE's parameter update from the successful F and CR values."""
+    f = np.array([muF], dtype=np.float64)
+    cr = np.array([muCR], dtype=np.float64)
+    SF, SCR = (np.ascontiguousarray(a, dtype=np.float64) for a in (SF, SCR))
+    lib().orc_jade_update(c, _d(f), _d(cr), SF.shape[0], _d(SF), _d(SCR))
+    return float(f[0]), float(cr[0])

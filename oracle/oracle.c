@@ -784,9 +784,24 @@ void orc_lshade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos, 
     *pos = (*pos + 1) % H;
 }
 
-int orc_lshade_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
-                          double p, double r_arc, int32_t np_next, uint32_t run_uid, uint64_t seed,
-                          uint32_t t, double *U, double *eU, int32_t *n_success)
+void orc_jade_update(double c, double *muF, double *muCR, int32_t n_s, const double *SF, const double *SCR)
+{
+    if (n_s <= 0) return;
+    double scr = 0.0, sf = 0.0, sf2 = 0.0;
+    for (int k = 0; k < n_s; ++k) {
+        scr += SCR[k];
+        sf += SF[k];
+        sf2 += SF[k] * SF[k];
+    }
+    *muCR = (1.0 - c) * *muCR + c * (scr / (double)n_s);   /* arithmetic mean */
+    *muF = (1.0 - c) * *muF + c * (sf2 / sf);               /* Lehmer mean */
+}
+
+/* One generation of L-SHADE (jade = 0) or JADE (jade = 1, adaptation rate
+ * c): the two differ only in the parameter update after the selection. */
+static int archive_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
+                              double p, double r_arc, int32_t np_next, int jade, double c, uint32_t run_uid,
+                              uint64_t seed, uint32_t t, double *U, double *eU, int32_t *n_success)
 {
     const int D = pb->dim, np = s->np;
     if (np < 4 || D < 1 || s->H < 1 || np_next < 4 || np_next > np) return -1;
@@ -867,7 +882,8 @@ int orc_lshade_generation(const orc_problem *pb, const double *o, const double *
             s->eX[i] = eU[i];
         }
     }
-    orc_lshade_memory_update(H, s->MF, s->MCR, &s->pos, n_s, SF, SCR, dS);
+    if (jade) orc_jade_update(c, &s->MF[0], &s->MCR[0], n_s, SF, SCR);
+    else orc_lshade_memory_update(H, s->MF, s->MCR, &s->pos, n_s, SF, SCR, dS);
     if (n_success) *n_success = n_s;
 
     /* population size reduction: keep the best np_next, in index order */
@@ -904,6 +920,21 @@ int orc_lshade_generation(const orc_problem *pb, const double *o, const double *
     }
     free(rank); free(v); free(Fi); free(tmp);
     return 0;
+}
+
+int orc_lshade_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
+                          double p, double r_arc, int32_t np_next, uint32_t run_uid, uint64_t seed,
+                          uint32_t t, double *U, double *eU, int32_t *n_success)
+{
+    return archive_generation(pb, o, M, s, p, r_arc, np_next, 0, 0.0, run_uid, seed, t, U, eU, n_success);
+}
+
+int orc_jade_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
+                        double p, double r_arc, double c, uint32_t run_uid, uint64_t seed, uint32_t t,
+                        double *U, double *eU, int32_t *n_success)
+{
+    if (s->H != 1) return -1;
+    return archive_generation(pb, o, M, s, p, r_arc, s->np, 1, c, run_uid, seed, t, U, eU, n_success);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1046,14 +1077,42 @@ static void record(recorder *r, double e, const double *x)
     }
 }
 
+/* Observer row g: (muF, muCR). */
+static void observe(double *mu, int64_t mu_len, int64_t g, double muF, double muCR)
+{
+    if (mu && g < mu_len) {
+        mu[2 * g] = muF;
+        mu[2 * g + 1] = muCR;
+    }
+}
+
+/* Observer row g of a success-history memory: the means of its H slots, a
+ * terminal CR slot (negative) counted as the CR of 0 it gives. */
+static void observe_memory(double *mu, int64_t mu_len, int64_t g, int H, const double *MF, const double *MCR)
+{
+    double f = 0.0, cr = 0.0;
+    for (int k = 0; k < H; ++k) {
+        f += MF[k];
+        cr += MCR[k] < 0.0 ? 0.0 : MCR[k];
+    }
+    observe(mu, mu_len, g, f / H, cr / H);
+}
+
 int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             orc_run_result *res, double *trace, int64_t trace_len, double *best_x)
+{
+    return orc_run_observed(d, seed, inst_seed, res, trace, trace_len, best_x, NULL, 0);
+}
+
+int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, orc_run_result *res,
+                     double *trace, int64_t trace_len, double *best_x, double *mu, int64_t mu_len)
 {
     int D = d->dim, np = d->np;
     if (D < 1 || np < 1) return -1;
     if ((d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE || d->algo == ORC_ALGO_LSHADE ||
-         d->algo == ORC_ALGO_PSODE) && np < 4)
+         d->algo == ORC_ALGO_PSODE || d->algo == ORC_ALGO_JADE) && np < 4)
         return -1;
+    for (int64_t k = 0; mu && k < 2 * mu_len; ++k) mu[k] = NAN;
     orc_problem pb = { d->func, D, d->lb, d->ub };
     size_t pop = (size_t)np * D;
     double *o = (double *)malloc(sizeof(double) * (size_t)D);
@@ -1099,6 +1158,8 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
         orc_init_population(&pb, np, d->run_uid, seed, X);
         orc_error_aos(d->func, D, o, M, X, np, eX);
         for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+        if (d->algo == ORC_ALGO_DE) observe(mu, mu_len, 0, d->F, d->CR);
+        else observe_memory(mu, mu_len, 0, H, MF, MCR);
         while (rec.fe < d->budget) {
             ++gens;
             if (d->algo == ORC_ALGO_DE)
@@ -1112,14 +1173,17 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             for (int i = 0; i < np; ++i) record(&rec, eU[i], U + (size_t)i * D);
             memcpy(X, Xn, sizeof(double) * pop);
             memcpy(eX, eXn, sizeof(double) * (size_t)np);
+            if (d->algo == ORC_ALGO_DE) observe(mu, mu_len, gens, d->F, d->CR);
+            else observe_memory(mu, mu_len, gens, H, MF, MCR);
         }
-    } else if (d->algo == ORC_ALGO_LSHADE) {
-        const int32_t np_min = d->np_min;
+    } else if (d->algo == ORC_ALGO_LSHADE || d->algo == ORC_ALGO_JADE) {
+        const int jade = d->algo == ORC_ALGO_JADE;
+        const int32_t np_min = jade ? np : d->np_min;
         if (np_min < 4 || np_min > np) { free(o); free(M); free(buf); return -1; }
         orc_lshade_state st;
         memset(&st, 0, sizeof(st));
         st.np = np;
-        st.H = d->H > 0 ? (d->H > 64 ? 64 : d->H) : 1;
+        st.H = jade ? 1 : d->H > 0 ? (d->H > 64 ? 64 : d->H) : 1;
         st.acap = orc_lshade_archive_max(d->r_arc, np) + 1;
         st.X = X;
         st.eX = eX;
@@ -1130,14 +1194,22 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
         orc_init_population(&pb, np, d->run_uid, seed, X);
         orc_error_aos(d->func, D, o, M, X, np, eX);
         for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+        observe_memory(mu, mu_len, 0, st.H, st.MF, st.MCR);
         while (rec.fe < d->budget) {
             ++gens;
             const int32_t np_old = st.np;
-            const int32_t np_next = orc_lshade_np(np, np_min, d->budget, rec.fe + np_old);
-            rc = orc_lshade_generation(&pb, o, M, &st, d->p, d->r_arc, np_next < np_old ? np_next : np_old,
-                                       d->run_uid, seed, (uint32_t)gens, U, eU, NULL);
+            if (jade) {
+                rc = orc_jade_generation(&pb, o, M, &st, d->p, d->r_arc, d->c, d->run_uid, seed,
+                                         (uint32_t)gens, U, eU, NULL);
+            } else {
+                const int32_t np_next = orc_lshade_np(np, np_min, d->budget, rec.fe + np_old);
+                rc = orc_lshade_generation(&pb, o, M, &st, d->p, d->r_arc,
+                                           np_next < np_old ? np_next : np_old, d->run_uid, seed,
+                                           (uint32_t)gens, U, eU, NULL);
+            }
             if (rc != 0) break;
             for (int i = 0; i < np_old; ++i) record(&rec, eU[i], U + (size_t)i * D);
+            observe_memory(mu, mu_len, gens, st.H, st.MF, st.MCR);
         }
         free(st.A);
     } else if (d->algo == ORC_ALGO_PSODE) {
@@ -1150,6 +1222,7 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
         orc_error_aos(d->func, D, o, M, X, np, eX);
         memset(V, 0, sizeof(double) * pop);
         for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+        observe_memory(mu, mu_len, 0, H, MF, MCR);
         while (rec.fe < d->budget) {
             ++gens;
             rc = orc_psode_generation(&pb, o, M, np, d->topology, d->velocity, d->w, d->c1, d->c2, d->vmax,
@@ -1158,6 +1231,7 @@ int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             if (rc != 0) break;
             for (int i = 0; i < np; ++i) record(&rec, eY[i], Y + (size_t)i * D);
             for (int i = 0; i < np; ++i) record(&rec, eU[i], U + (size_t)i * D);
+            observe_memory(mu, mu_len, gens, H, MF, MCR);
         }
     } else if (d->algo == ORC_ALGO_CSO) {
         double *V = A, *G = B, *eG = eA;

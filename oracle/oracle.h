@@ -32,7 +32,7 @@ extern "C" {
 enum { ORC_ELLIPSOID = 0, ORC_ROSENBROCK = 1, ORC_RASTRIGIN = 2,
        ORC_SCHWEFEL = 3, ORC_GRIEWANK = 4, ORC_ACKLEY = 5, ORC_NFUNC = 6 };
 enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3, ORC_ALGO_PSODE = 4,
-       ORC_ALGO_CSO = 5 };
+       ORC_ALGO_CSO = 5, ORC_ALGO_JADE = 6 };
 
 /* Philox stream tags (third counter word, bits 24..31). */
 enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
@@ -185,6 +185,25 @@ int orc_lshade_generation(const orc_problem *pb, const double *o, const double *
 void orc_lshade_memory_update(int32_t H, double *MF, double *MCR, int32_t *pos, int32_t n_s,
                               const double *SF, const double *SCR, const double *dS);
 
+/* ---- JADE (Zhang and Sanderson 2009), the algorithm whose adaptive
+ * parameters muF and muCR the paper's second case study observes (Sec. 4,
+ * Fig. 9) ----
+ * The state is an orc_lshade_state with H = 1: MF[0] = muF, MCR[0] = muCR.
+ * One generation is L-SHADE's (ranking, draws from slot 0 -- CR ~ N(muCR,
+ * 0.1) clipped to [0, 1], F ~ Cauchy(muF, 0.1) redrawn while <= 0 and capped
+ * at 1 --, current-to-pbest/1 with r2 from the population and the archive,
+ * crossover, repair, selection, the archive of improved parents bounded by
+ * round(r_arc np)) with no population reduction and JADE's parameter
+ * update in place of the memory:
+ *   muCR <- (1 - c) muCR + c mean(S_CR),
+ *   muF  <- (1 - c) muF  + c sum(S_F^2) / sum(S_F),
+ * plain (unweighted) means over the strictly improved individuals; nothing
+ * changes when none improved. */
+void orc_jade_update(double c, double *muF, double *muCR, int32_t n_s, const double *SF, const double *SCR);
+int orc_jade_generation(const orc_problem *pb, const double *o, const double *M, orc_lshade_state *s,
+                        double p, double r_arc, double c, uint32_t run_uid, uint64_t seed, uint32_t t,
+                        double *U, double *eU, int32_t *n_success);
+
 /* ---- PSODE: the PSO/DE hybrid with pairwise/3 selection of the case study
  * (Sec. 4, Listing 4) ----
  * One generation from the population X / eX and the velocities V:
@@ -243,8 +262,11 @@ typedef struct {
     int32_t np_min;        /* L-SHADE: final population size */
     int32_t topology;      /* PSO: 0 global best, 1 ring */
     int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical */
+    double c;              /* JADE: adaptation rate of muF and muCR */
 } orc_run_desc;
-/* CSO runs take np = m (even) and phi in c1; V starts at zero; an iteration
+/* JADE runs take p, r_arc (the archive bound per individual: 1 in JADE) and
+ * c; H and np_min are ignored (one parameter pair, no reduction).
+ * CSO runs take np = m (even) and phi in c1; V starts at zero; an iteration
  * makes m/2 evaluations, recorded in pair order.
  * PSODE runs take the PSO fields (w, c1, c2, vmax, topology, velocity) and
  * SHADE's (p, H); V starts at zero; a generation makes 2 np evaluations,
@@ -260,6 +282,17 @@ typedef struct {
 #define ORC_TRACE_EVERY 200
 int orc_run(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed,
             orc_run_result *res, double *trace, int64_t trace_len, double *best_x);
+
+/* orc_run with the parameter observer of the second case study (Sec. 4,
+ * Fig. 9): mu[2g], mu[2g+1] (g < mu_len) receive (muF, muCR) after g
+ * generations (g = 0: the initial state), NaN for generations not made.
+ *   JADE: its muF and muCR;
+ *   SHADE, L-SHADE, PSODE: the means of the H memory slots (a terminal CR
+ *   slot counts as 0, the CR it gives);
+ *   DE: its fixed F and CR;
+ *   PSO, CSO: NaN (no such parameters). */
+int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, orc_run_result *res,
+                     double *trace, int64_t trace_len, double *best_x, double *mu, int64_t mu_len);
 
 /* Constants of the Schwefel form (the argmax s and c = s sin sqrt s). */
 double orc_schwefel_s(void);

@@ -756,3 +756,149 @@ def test_cso_update_draws_are_independent():
     c = 12 * c
     assert np.all(np.abs(c[:3] - [1, 1, phi ** 2]) < 0.3)
     assert np.all(np.abs(c[3:]) < 0.8)
+
+
+# ------------------------------------------------------------------ JADE and the parameter observer
+
+def test_jade_update_closed_form():
+    """JADE's update on a hand-built success set: muCR moves a fraction c
+    towards the plain mean of S_CR, muF towards the Lehmer mean of S_F."""
+    # S_CR = {0.3, 0.9}: mean 0.6; S_F = {0.2, 0.6}: (0.04 + 0.36) / 0.8 = 0.5
+    f, cr = O.jade_update(0.1, 0.5, 0.5, [0.2, 0.6], [0.3, 0.9])
+    assert cr == pytest.approx(0.51, abs=1e-15)
+    assert f == pytest.approx(0.5, abs=1e-15)
+    # c = 1: the means themselves; a single success: its own values
+    assert O.jade_update(1.0, 0.5, 0.5, [0.8], [0.1]) == pytest.approx((0.8, 0.1), abs=1e-15)
+    # c = 0 or an empty set: unchanged
+    assert O.jade_update(0.0, 0.3, 0.7, [0.9], [0.2]) == (0.3, 0.7)
+    assert O.jade_update(0.1, 0.3, 0.7, [], []) == (0.3, 0.7)
+    # unweighted: repeating a success does not move the means
+    assert O.jade_update(0.5, 0.5, 0.5, [0.2, 0.6, 0.6, 0.2], [0.3, 0.9, 0.9, 0.3]) == \
+        pytest.approx(O.jade_update(0.5, 0.5, 0.5, [0.2, 0.6], [0.3, 0.9]), abs=1e-15)
+
+
+@pytest.mark.parametrize("c", [0.1, 1.0])
+def test_jade_first_generation_is_shades_with_one_slot(c):
+    """JADE's first generation draws from its one parameter pair exactly as
+    SHADE with a one-slot memory (empty archive): the same trials, errors
+    and population; its update then follows from SHADE's own F, CR and
+    success flags by JADE's rule."""
+    func, D, np_, p = O.ELLIPSOID, 10, 50, 0.05
+    o, M, X, eX = _pop(func, D, np_)
+    ref = O.shade_generation(func, LB, UB, o, M, X, eX, np.full(1, 0.5), np.full(1, 0.5), 0, p, 7, SEED, 1)
+    jd = O.LShade(func, D, LB, UB, o, M, X, eX, H=1, r_arc=1.0)
+    U, eU, ns = jd.jade_generation(p, c, 7, SEED, 1)
+    assert np.array_equal(U, ref["U"]) and np.array_equal(eU, ref["eU"])
+    assert np.array_equal(jd.X[:np_], ref["X"]) and np.array_equal(jd.eX[:np_], ref["eX"])
+    succ = ref["eU"] < eX
+    assert ns == int(succ.sum()) and ns > 0 and jd.na == ns
+    SF, SCR = ref["F"][succ], ref["CR"][succ]
+    mf, mcr, _ = jd.memory()
+    assert mcr[0] == pytest.approx((1 - c) * 0.5 + c * SCR.mean(), rel=1e-14)
+    assert mf[0] == pytest.approx((1 - c) * 0.5 + c * (SF ** 2).sum() / SF.sum(), rel=1e-14)
+
+
+def test_jade_archive_bound_and_fixed_population():
+    """Over many generations JADE keeps its population size, the archive
+    stays within round(r_arc NP) and holds only former members, muF stays in
+    (0, 1] and muCR in [0, 1]."""
+    func, D, np_, r_arc = O.RASTRIGIN, 6, 30, 1.0
+    o, M, X, eX = _pop(func, D, np_)
+    jd = O.LShade(func, D, LB, UB, o, M, X, eX, H=1, r_arc=r_arc)
+    seen = {tuple(x) for x in X}
+    for t in range(1, 80):
+        before = jd.eX[:np_].copy()
+        U, eU, ns = jd.jade_generation(0.05, 0.1, 4, SEED, t)
+        seen |= {tuple(x) for x in U}
+        assert jd.np == np_
+        assert np.all(jd.eX[:np_] <= before)
+        assert jd.na <= O.lshade_archive_max(r_arc, np_)
+        for a in jd.A[:jd.na]:
+            assert tuple(a) in seen
+        mf, mcr, _ = jd.memory()
+        assert 0.0 < mf[0] <= 1.0 and 0.0 <= mcr[0] <= 1.0
+    assert jd.na == O.lshade_archive_max(r_arc, np_)   # full after 79 generations
+
+
+def _jade_desc(func, D, np_, budget, c=0.1, **kw):
+    return _desc(O.ALGO_JADE, func, D, np_, budget, p=0.05, r_arc=1.0, c=c, H=1, np_min=4, **kw)
+
+
+def test_jade_run_matches_generations_and_observer():
+    """The run driver's JADE run is the generation function stepped by hand:
+    same evaluations (count, best, trace) and observer rows equal to the
+    parameter pair after each generation, NaN beyond."""
+    func, D, np_, budget = O.GRIEWANK, 5, 20, 1000
+    d = _jade_desc(func, D, np_, budget)
+    gens = -(-(budget - np_) // np_)
+    res, trace, _, mu = O.run(d, SEED, ISEED, trace_len=budget // 200, mu_len=gens + 3)
+    o, M = O.instance(func, D, 0, ISEED)
+    X = O.init_population(func, D, LB, UB, np_, 1, SEED)
+    eX = O.errors(func, o, M, X)
+    jd = O.LShade(func, D, LB, UB, o, M, X, eX, H=1, r_arc=1.0)
+    evals = list(eX)
+    rows = [(0.5, 0.5)]
+    for t in range(1, gens + 1):
+        U, eU, _ = jd.jade_generation(0.05, 0.1, 1, SEED, t)
+        evals += list(eU)
+        mf, mcr, _ = jd.memory()
+        rows.append((mf[0], mcr[0]))
+    e = np.array(evals)
+    assert res["fes"] == len(e) and res["generations"] == gens
+    assert res["best_e"] == e[:budget].min()
+    assert np.array_equal(trace, [e[: 200 * (k + 1)].min() for k in range(budget // 200)])
+    assert np.array_equal(mu[: gens + 1], np.array(rows))
+    assert np.all(np.isnan(mu[gens + 1:]))
+    # rows move: the parameters adapt
+    assert len({tuple(r) for r in rows}) > gens // 2
+
+
+def test_observer_rows_per_algorithm():
+    """Observer rows: DE its fixed (F, CR); SHADE and PSODE the means of the
+    memory slots, from (0.5, 0.5); PSO and CSO NaN; rows replayed from
+    SHADE's generation function."""
+    func, D, np_, budget = O.RASTRIGIN, 5, 20, 610
+    gens = -(-(budget - np_) // np_)   # whole generations: 30
+    _, _, _, mu = O.run(_desc(O.ALGO_DE, func, D, np_, budget, F=0.7, CR=0.3), SEED, ISEED, mu_len=gens + 2)
+    assert np.array_equal(mu[: gens + 1], np.tile([0.7, 0.3], (gens + 1, 1)))
+    assert np.all(np.isnan(mu[gens + 1:]))
+    for algo in (O.ALGO_PSO, O.ALGO_CSO):
+        _, _, _, mu = O.run(_desc(algo, func, D, np_, budget), SEED, ISEED, mu_len=5)
+        assert np.all(np.isnan(mu))
+    # SHADE: replay the memory by hand
+    _, _, _, mu = O.run(_desc(O.ALGO_SHADE, func, D, np_, budget, H=3), SEED, ISEED, mu_len=gens + 1)
+    o, M = O.instance(func, D, 0, ISEED)
+    X = O.init_population(func, D, LB, UB, np_, 1, SEED)
+    eX = O.errors(func, o, M, X)
+    MF = np.full(3, 0.5); MCR = np.full(3, 0.5); pos = 0
+    assert tuple(mu[0]) == (0.5, 0.5)
+    for t in range(1, gens + 1):
+        out = O.shade_generation(func, LB, UB, o, M, X, eX, MF, MCR, pos, 0.1, 1, SEED, t)
+        MF, MCR, pos, X, eX = out["MF"], out["MCR"], out["pos"], out["X"], out["eX"]
+        assert mu[t] == pytest.approx([MF.mean(), MCR.mean()], rel=1e-15)
+    # PSODE: rows start at (0.5, 0.5) and stay in range
+    _, _, _, mu = O.run(_desc(O.ALGO_PSODE, func, D, np_, budget), SEED, ISEED, mu_len=8)
+    assert tuple(mu[0]) == (0.5, 0.5) and np.all((mu[1:] > 0) & (mu[1:] <= 1))
+
+
+def test_observer_counts_a_terminal_cr_slot_as_zero():
+    """L-SHADE's terminal CR slot (set when every successful CR was 0) gives
+    CR = 0, and the observer counts it as 0: rows of a long L-SHADE run
+    replayed from the generation function."""
+    MF, MCR, pos = O.lshade_memory_update(np.full(2, 0.5), np.full(2, 0.5), 0, [0.4], [0.0], [1.0])
+    assert MCR[0] < 0                               # terminal
+    # a run found (by a scan over functions and run ids) to reach a
+    # terminal slot in generation 47
+    func, D, np_, gens, uid = O.ROSENBROCK, 4, 8, 100, 16
+    d = _desc(O.ALGO_LSHADE, func, D, np_, np_ * (gens + 1), p=0.11, H=2, r_arc=1.0, np_min=np_, run_uid=uid)
+    _, _, _, mu = O.run(d, SEED, ISEED, mu_len=gens + 1)
+    o, M = O.instance(func, D, 0, ISEED)
+    X = O.init_population(func, D, LB, UB, np_, uid, SEED)
+    ls = O.LShade(func, D, LB, UB, o, M, X, O.errors(func, o, M, X), H=2, r_arc=1.0)
+    terminal = 0
+    for t in range(1, gens + 1):
+        ls.generation(0.11, np_, uid, SEED, t)
+        mf, mcr, _ = ls.memory()
+        terminal += int(np.any(mcr < 0))
+        assert mu[t] == pytest.approx([mf.mean(), np.where(mcr < 0, 0.0, mcr).mean()], rel=1e-15)
+    assert terminal > 0
