@@ -21,7 +21,10 @@
  *     record every 200 evaluations (Sec. 2.4, Sec. 3.2); also L-SHADE, the
  *     SHADE variant with an external archive and population size reduction
  *     that the DE module's archive and reduction mechanisms make (Sec. 2.2,
- *     and the L-SHADE family of Sec. 4).
+ *     and the L-SHADE family of Sec. 4);
+ *   - sevo_run_observed: sevo_run with the suite observer that follows the
+ *     adaptive parameters muF and muCR through each run (Sec. 4, second case
+ *     study, Fig. 9), for JADE and the success-history family.
  *
  * Conventions shared by every call
  *   - Status: every call returns SEVO_OK (0) or a negative SEVO_E* code and
@@ -81,7 +84,7 @@ enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFE
 enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
 
 enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3, SEVO_ALGO_PSODE = 4,
-       SEVO_ALGO_CSO = 5 };
+       SEVO_ALGO_CSO = 5, SEVO_ALGO_JADE = 6 };
 
 typedef struct sevo_ctx sevo_ctx;   /* opaque, library-owned */
 
@@ -251,13 +254,15 @@ typedef struct {
     int64_t budget;        /* function evaluations; whole generations are run */
     double F, CR;          /* DE */
     double w, c1, c2, vmax;/* PSO, PSODE; CSO: c1 = phi, the pull towards the swarm mean */
-    double p;              /* SHADE, L-SHADE, PSODE: pbest fraction (top max(2, round(p NP))) */
+    double p;              /* SHADE, L-SHADE, PSODE, JADE: pbest fraction (top max(2, round(p NP))) */
     int32_t H;             /* SHADE, L-SHADE, PSODE: memory size (1 .. 16) */
-    double r_arc;          /* L-SHADE: archive bound round(r_arc NP), 0 .. 2.9 (2.6 in L-SHADE) */
+    double r_arc;          /* L-SHADE, JADE: archive bound round(r_arc NP), 0 .. 2.9 (2.6 in L-SHADE,
+                              1 in JADE) */
     int32_t np_min;        /* L-SHADE: population size at the budget, 4 .. np */
     int32_t topology;      /* PSO, PSODE: 0 global best, 1 ring {i-1, i, i+1} (FP32 runs) */
     int32_t velocity;      /* PSO, PSODE: 0 inertia weight, 1 spherical (SPSO-2011; FP32 runs) */
     int32_t reserved;      /* 0 */
+    double c;              /* JADE: adaptation rate of muF and muCR, 0 .. 1 (0.1 in JADE) */
 } sevo_run_desc;
 
 typedef struct {
@@ -299,6 +304,13 @@ typedef struct {
  *   move where strictly better than the DE result.  2 np evaluations per
  *   generation, recorded as the PSO moves, then the DE trials; velocities
  *   start at 0.
+ *   JADE (Zhang and Sanderson 2009; the algorithm of the parameter
+ *   observer case study, Sec. 4; FP32 runs, np >= 4): L-SHADE's generation
+ *   with one parameter pair (muF, muCR) in place of the memory (H is
+ *   ignored), no population reduction (np_min is ignored) and the archive
+ *   bound round(r_arc np); after each generation muCR <- (1 - c) muCR +
+ *   c mean(S_CR) and muF <- (1 - c) muF + c sum(S_F^2) / sum(S_F), plain
+ *   means over the strictly improved individuals (no change when none).
  *   CSO (the competitive swarm optimizer of the large-scale study, Sec. 3.3;
  *   precision FP32 or SPLIT_BF16, any D up to 1024): per iteration the
  *   swarm is paired at random (ascending Philox key), the lower error of a
@@ -315,6 +327,21 @@ typedef struct {
 int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
              sevo_run_result *results, float *trace, int64_t trace_len,
              double *best_x, int32_t max_dim, void *stream);
+
+/* sevo_run with the parameter observer of the second case study (Sec. 4,
+ * Fig. 9: the adaptive muF and muCR of JADE followed through a run).
+ *   mu       optional device [n_runs][mu_len][2] float: (muF, muCR) after g
+ *            generations in row g (row 0: the initial values), NaN for
+ *            generations the run did not make.  JADE: its parameter pair;
+ *            SHADE, L-SHADE, PSODE: the means of the H memory slots (a
+ *            terminal CR slot counts as 0, the CR it gives); DE: its fixed
+ *            F and CR; PSO: NaN.
+ *   mu_len   rows per run, >= 0 (0: no observer, as sevo_run).
+ * Precision FP32 only (the fused kernels), and no CSO runs: otherwise
+ * SEVO_EUNSUPPORTED.  Everything else as sevo_run.  Asynchronous. */
+int sevo_run_observed(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+                      sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
+                      int32_t max_dim, float *mu, int64_t mu_len, void *stream);
 
 /* ---- plans: work prepared once, then enqueued with launches only ----
  *

@@ -32,11 +32,11 @@ int32_t shade_pnum(double p, int32_t np)
     return (int32_t)k;
 }
 
-// Archive slots of an L-SHADE run (its bound at the initial population,
-// plus one); 0 for the other algorithms.
+// Archive slots of an L-SHADE or JADE run (its bound at the initial
+// population, plus one); 0 for the other algorithms.
 int archive_cap(const sevo_run_desc &d)
 {
-    if (d.algo != SEVO_ALGO_LSHADE) return 0;
+    if (d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_JADE) return 0;
     return (int)std::lround(d.r_arc * (double)d.np) + 1;
 }
 
@@ -53,7 +53,8 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
         if (p.func < 0 || p.func >= NFUNC || p.dim < 2 || p.dim > MAX_DIM || !(p.lb < p.ub))
             return set_error(ctx, SEVO_EINVAL, "run has an invalid problem");
         if (d.algo != SEVO_ALGO_DE && d.algo != SEVO_ALGO_PSO && d.algo != SEVO_ALGO_SHADE &&
-            d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_PSODE && d.algo != SEVO_ALGO_CSO)
+            d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_PSODE && d.algo != SEVO_ALGO_CSO &&
+            d.algo != SEVO_ALGO_JADE)
             return set_error(ctx, SEVO_EINVAL, "unknown algorithm");
         if (d.algo == SEVO_ALGO_CSO) {
             // CSO: the update kernels and the batched evaluation, any D
@@ -81,6 +82,9 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             return set_error(ctx, SEVO_EINVAL, "SHADE needs H in [1, 16] and p in (0, 1]");
         if (d.algo == SEVO_ALGO_LSHADE && (d.np_min < 4 || d.np_min > d.np || !(d.r_arc >= 0 && d.r_arc <= 2.9)))
             return set_error(ctx, SEVO_EINVAL, "L-SHADE needs np_min in [4, np] and r_arc in [0, 2.9]");
+        if (d.algo == SEVO_ALGO_JADE &&
+            (!(d.p > 0 && d.p <= 1) || !(d.r_arc >= 0 && d.r_arc <= 2.9) || !(d.c >= 0 && d.c <= 1)))
+            return set_error(ctx, SEVO_EINVAL, "JADE needs p in (0, 1], r_arc in [0, 2.9] and c in [0, 1]");
         if (best_x && max_dim < p.dim) return set_error(ctx, SEVO_EINVAL, "max_dim < dim");
         if (precision == SEVO_FP32 && p.dim > SMALL_D_MAX)
             return set_error(ctx, SEVO_EUNSUPPORTED, "fused runs support D <= 120");
@@ -88,8 +92,8 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             return set_error(ctx, SEVO_EINVAL, "PSO topology and velocity are 0 or 1");
         if (precision == SEVO_FP64 && d.algo == SEVO_ALGO_PSO && (d.topology != 0 || d.velocity != 0))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision PSO is global-best inertia");
-        if (precision == SEVO_FP64 &&
-            (d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE || d.algo == SEVO_ALGO_PSODE))
+        if (precision == SEVO_FP64 && (d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE ||
+                                       d.algo == SEVO_ALGO_PSODE || d.algo == SEVO_ALGO_JADE))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision run path has DE and PSO");
     }
     return SEVO_OK;
@@ -126,7 +130,7 @@ static size_t onchip_limit(int ks, bool wave, int fam)
 }
 
 int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *results, float *trace,
-              int64_t trace_len, double *best_x, int max_dim, hipStream_t stream)
+              int64_t trace_len, double *best_x, int max_dim, float *mu, int64_t mu_len, hipStream_t stream)
 {
     // Team: runs of up to 64 individuals get one wave each (four runs of
     // one instance per workgroup), larger ones a whole workgroup.
@@ -187,7 +191,7 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.np = d.np;
         R.npp = (d.np + 15) & ~15;
         R.run_uid = d.run_uid;
-        R.H = d.H;
+        R.H = d.algo == SEVO_ALGO_JADE ? 1 : d.H;
         R.pnum = d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_PSODE ? shade_pnum(d.p, d.np) : 0;
         R.budget = d.budget;
         R.F = (float)d.F;
@@ -216,7 +220,7 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.velocity = pso_like ? d.velocity : 0;
         R.p = d.p;
         R.r_arc = d.r_arc;
-        R.np_min = d.np_min;
+        R.np_min = d.algo == SEVO_ALGO_JADE ? d.np : d.np_min;
         R.acap = archive_cap(d);
         R.Arc = R.acap > 0 ? R.bestx + R.dim : nullptr;
         R.res = results;
@@ -225,6 +229,10 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.best_x_out = best_x;
         R.max_dim = max_dim;
         R.out_index = r;
+        R.mu = mu_len > 0 ? mu : nullptr;
+        R.mu_len = mu_len;
+        R.c_adapt = d.c;
+        R.CR = (float)d.CR;
         Group &G = groups[(ks_of(R.dim) * NFAM + family_of(d.algo)) * 4 + onchip[r] * 2 + wave[r]];
         G.runs.push_back(R);
         G.cost.push_back((double)d.budget * R.dim * R.dim);
@@ -292,12 +300,15 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
 // Single-precision runs: the fused kernels for DE, SHADE, L-SHADE, PSO and
 // PSODE, the update-and-evaluate loop for CSO.
 int run_single(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision, sevo_run_result *results,
-               float *trace, int64_t trace_len, double *best_x, int max_dim, hipStream_t stream)
+               float *trace, int64_t trace_len, double *best_x, int max_dim, hipStream_t stream,
+               float *mu = nullptr, int64_t mu_len = 0)
 {
     bool fused = false;
     for (int r = 0; r < n; ++r) fused |= runs[r].algo != SEVO_ALGO_CSO;
     int rc = SEVO_OK;
-    if (fused && (rc = run_fused(ctx, runs, n, results, trace, trace_len, best_x, max_dim, stream))) return rc;
+    if (fused &&
+        (rc = run_fused(ctx, runs, n, results, trace, trace_len, best_x, max_dim, mu, mu_len, stream)))
+        return rc;
     return cso_runs(ctx, runs, n, precision, results, trace, trace_len, best_x, max_dim, stream);
 }
 
@@ -345,5 +356,28 @@ extern "C" int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs
     if (precision != SEVO_FP64)
         return run_single(ctx, runs, n_runs, precision, results, trace, trace_len, best_x, max_dim,
                           (hipStream_t)stream);
+    return run_plain_f64(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, (hipStream_t)stream);
+}
+
+extern "C" int sevo_run_observed(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+                                 sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
+                                 int32_t max_dim, float *mu, int64_t mu_len, void *stream)
+{
+    if (!ctx) return set_error(nullptr, SEVO_EINVAL, "ctx is NULL");
+    if (!results) return set_error(ctx, SEVO_EINVAL, "results is NULL");
+    if (mu_len < 0 || (mu_len > 0 && !mu)) return set_error(ctx, SEVO_EINVAL, "bad observer buffer");
+    int rc = validate_runs(ctx, runs, n_runs, precision, trace_len, trace, best_x, max_dim);
+    if (rc) return rc;
+    if (mu_len > 0) {
+        if (precision != SEVO_FP32)
+            return set_error(ctx, SEVO_EUNSUPPORTED, "the parameter observer records FP32 runs");
+        for (int r = 0; r < n_runs; ++r)
+            if (runs[r].algo == SEVO_ALGO_CSO)
+                return set_error(ctx, SEVO_EUNSUPPORTED, "the parameter observer records no CSO runs");
+    }
+    DeviceScope dg(ctx);
+    if (precision != SEVO_FP64)
+        return run_single(ctx, runs, n_runs, precision, results, trace, trace_len, best_x, max_dim,
+                          (hipStream_t)stream, mu, mu_len);
     return run_plain_f64(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, (hipStream_t)stream);
 }

@@ -61,6 +61,12 @@ struct RunDev {
     double *best_x_out;
     int32_t max_dim;
     int32_t out_index;
+    // parameter observer: rows (muF, muCR) after each generation, or null;
+    // JADE's adaptation rate; DE's CR for the observer rows
+    float *mu;
+    int64_t mu_len;
+    double c_adapt;
+    float CR;
 };
 
 // A team carries one run: the whole workgroup (256 threads, phases separated
@@ -378,7 +384,7 @@ inline int family_of(int algo)
 {
     return algo == SEVO_ALGO_PSO ? FAM_PSO
          : algo == SEVO_ALGO_SHADE ? FAM_SHADE
-         : algo == SEVO_ALGO_LSHADE ? FAM_LSHADE
+         : algo == SEVO_ALGO_LSHADE || algo == SEVO_ALGO_JADE ? FAM_LSHADE
          : algo == SEVO_ALGO_PSODE ? FAM_PSODE
                                     : FAM_DE;
 }
@@ -441,6 +447,9 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     // then the pairwise/3 selection
     constexpr bool psode = FAM == FAM_PSODE;
     constexpr bool shade = FAM == FAM_SHADE || lshade || psode;
+    // JADE runs in the L-SHADE kernel: one parameter pair (H = 1), no
+    // reduction (np_min = np), its own parameter update
+    const bool jade = lshade && R.algo == SEVO_ALGO_JADE;
     constexpr bool moves = pso || psode;   // makes a PSO move each generation
     // X population; U DE trials; V velocities; P personal bests (PSODE: the
     // population itself); Y where the PSO move goes (PSO: in place)
@@ -548,9 +557,34 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
         t.sync();
     };
 
+    // parameter observer row g: JADE's pair, the memory means of the
+    // success-history family (a terminal CR slot counts as 0), DE's fixed
+    // F and CR, NaN for PSO
+    auto observe = [&](int g) {
+        if (tid == 0 && R.mu && g < R.mu_len) {
+            float mf = NAN, mcr = NAN;
+            if (shade) {
+                double f = 0.0, cr = 0.0;
+                for (int k = 0; k < R.H; ++k) {
+                    f += (double)sMF[k];
+                    cr += sMCR[k] < 0.f ? 0.0 : (double)sMCR[k];
+                }
+                mf = (float)(f / R.H);
+                mcr = (float)(cr / R.H);
+            } else if (!moves) {
+                mf = R.F;
+                mcr = R.CR;
+            }
+            float *row = R.mu + ((int64_t)R.out_index * R.mu_len + g) * 2;
+            row[0] = mf;
+            row[1] = mcr;
+        }
+    };
+
     eval_pop<KS, ONCHIP>(t, R, np, X, sEX, sA, sO, sT, K);
     t.sync();
     record(X, sEX);
+    observe(0);
     if (pso) {
         if (tid < np) sEP[tid] = sEX[tid];
         t.sync();
@@ -745,7 +779,8 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                 const float ku = err_key(sEU[tid]), kx = err_key(sEX[tid]);
                 succ = ku < kx;
                 if (shade && succ) {
-                    double dl = (double)kx - (double)ku;
+                    // JADE: plain means (weight 1); the others weight by the improvement
+                    double dl = jade ? 1.0 : (double)kx - (double)ku;
                     if (!(dl <= 1e30)) dl = 1e30;
                     const double cr = sCR[tid], f = sF[tid];
                     st[0] = dl;
@@ -829,7 +864,12 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
             }
             if (shade) {
                 team_sums<NSUM>(t, st, sRed);
-                if (tid == 0 && st[5] > 0.0) {
+                if (tid == 0 && st[5] > 0.0 && jade) {
+                    // muCR towards the mean of S_CR, muF towards the Lehmer mean of S_F
+                    const double c = R.c_adapt;
+                    sMCR[0] = (float)((1.0 - c) * (double)sMCR[0] + c * (st[1] / st[0]));
+                    sMF[0] = (float)((1.0 - c) * (double)sMF[0] + c * (st[3] / st[4]));
+                } else if (tid == 0 && st[5] > 0.0) {
                     const int pos = sPosA[s];
                     if (lshade)   // weighted Lehmer mean; terminal value kept or set
                         sMCR[pos] = (sMCR[pos] < 0.f || st[6] == 0.0) ? -1.f : (float)(st[2] / st[1]);
@@ -840,6 +880,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                 }
                 t.sync();
             }
+            observe(gen);
             if (psode && R.topology == 0) global_best(sEX);
             if (lshade) {
                 // linear population size reduction: the best nn stay, in index order
@@ -897,6 +938,14 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
         }
         fe += np;
     }
+
+    // observer rows of generations not made (PSO: every row) are NaN
+    if (R.mu)
+        for (int64_t g = (pso ? 0 : gen + 1) + tid; g < R.mu_len; g += TS) {
+            float *row = R.mu + ((int64_t)R.out_index * R.mu_len + g) * 2;
+            row[0] = NAN;
+            row[1] = NAN;
+        }
 
     // results; the best point is re-evaluated in double once below 1e-6
     const float be = sBestBA[s];

@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
 FP64, FP32, SPLIT_BF16 = 0, 1, 2
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO = 0, 1, 2, 3, 4, 5
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO, ALGO_JADE = 0, 1, 2, 3, 4, 5, 6
 TRACE_EVERY = 200
 
 
@@ -72,7 +72,7 @@ class RunDesc(C.Structure):
                 ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
                 ("p", C.c_double), ("H", C.c_int32),
                 ("r_arc", C.c_double), ("np_min", C.c_int32), ("topology", C.c_int32),
-                ("velocity", C.c_int32), ("reserved", C.c_int32)]
+                ("velocity", C.c_int32), ("reserved", C.c_int32), ("c", C.c_double)]
 
 
 class RunResult(C.Structure):
@@ -114,6 +114,7 @@ def lib():
     L.sevo_pso_step.argtypes = [vp, C.POINTER(Problem), u32, C.POINTER(PSOState),
                                 C.POINTER(PSOParams), i32, vp]
     L.sevo_run.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, vp]
+    L.sevo_run_observed.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, vp, i64, vp]
     L.sevo_plan_evaluate.argtypes = [vp, C.POINTER(EvalItem), i32, i32, C.POINTER(vp)]
     L.sevo_plan_run.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, C.POINTER(vp)]
     L.sevo_plan_launch.argtypes = [vp, vp]
@@ -292,3 +293,11 @@ class Context:
         self._check(self._L.sevo_run(self._h, arr, len(descs), precision, _ptr(results),
                                      _ptr(trace), trace_len, _ptr(best_x), max_dim,
                                      _stream(stream)))
+
+    def run_observed(self, descs, results, mu, mu_len, trace=None, trace_len=0, best_x=None, max_dim=0,
+                     precision=FP32, stream=None):
+        """sevo_run_observed: `mu` a device float buffer of n_runs * mu_len * 2."""
+        arr = (RunDesc * len(descs))(*descs)
+        self._check(self._L.sevo_run_observed(self._h, arr, len(descs), precision, _ptr(results),
+                                              _ptr(trace), trace_len, _ptr(best_x), max_dim, _ptr(mu),
+                                              mu_len, _stream(stream)))
