@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO, ALGO_JADE = 0, 1, 2, 3, 4, 5, 6
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO, ALGO_JADE, ALGO_LSHADE_RS = range(8)
 TRACE_EVERY = 200
 
 
@@ -54,7 +54,7 @@ class RunDesc(C.Structure):
         ("p", C.c_double), ("H", C.c_int32),
         ("r_arc", C.c_double), ("np_min", C.c_int32),
         ("topology", C.c_int32), ("velocity", C.c_int32),
-        ("c", C.c_double),
+        ("c", C.c_double), ("restart_tol", C.c_double),
     ]
 
 
@@ -66,7 +66,7 @@ class _LShadeState(C.Structure):
 
 class RunResult(C.Structure):
     _fields_ = [("best_e", C.c_double), ("fes", C.c_int64), ("generations", C.c_int32),
-                ("success", C.c_int32)]
+                ("success", C.c_int32), ("restarts", C.c_int32)]
 
 
 _lib = None
@@ -138,6 +138,9 @@ def lib():
                               dp, C.c_int64, dp]
         L.orc_run_observed.argtypes = [C.POINTER(RunDesc), C.c_uint64, C.c_uint64, C.POINTER(RunResult),
                                        dp, C.c_int64, dp, dp, C.c_int64]
+        L.orc_restart_population.argtypes = [pp, C.c_int32, C.c_uint32, C.c_uint64, C.c_uint32, dp]
+        L.orc_restart_population.restype = None
+        L.orc_converged.argtypes = [dp, C.c_int32, C.c_double]
         L.orc_jade_update.argtypes = [C.c_double, dp, dp, C.c_int32, dp, dp]
         L.orc_jade_update.restype = None
         L.orc_jade_generation.argtypes = [pp, dp, dp, C.POINTER(_LShadeState), C.c_double, C.c_double,
@@ -510,7 +513,7 @@ def run(desc: dict, seed, inst_seed, trace_len=0, mu_len=None):
     if rc != 0:
         raise ValueError("orc_run failed")
     out = (dict(best_e=res.best_e, fes=res.fes, generations=res.generations,
-                success=bool(res.success)), trace, best_x)
+                success=bool(res.success), restarts=res.restarts), trace, best_x)
     return out if mu_len is None else out + (mu,)
 
 
@@ -521,3 +524,15 @@ def jade_update(c, muF, muCR, SF, SCR):
     SF, SCR = (np.ascontiguousarray(a, dtype=np.float64) for a in (SF, SCR))
     lib().orc_jade_update(c, _d(f), _d(cr), SF.shape[0], _d(SF), _d(SCR))
     return float(f[0]), float(cr[0])
+
+
+def restart_population(func, dim, lb, ub, np_, run_uid, seed, k):
+    """Population of restart k ([np, dim]); k = 0 is the initial one."""
+    X = np.zeros((np_, dim))
+    lib().orc_restart_population(C.byref(_Problem(func, dim, lb, ub)), np_, run_uid, C.c_uint64(seed), k, _d(X))
+    return X
+
+
+def converged(e, tol):
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    return bool(lib().orc_converged(_d(e), e.shape[0], tol))

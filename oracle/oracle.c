@@ -342,16 +342,22 @@ void orc_error_aos(int32_t func, int32_t dim, const double *o, const double *M,
 
 /* ------------------------------------------------------------------------- */
 /* Population initialisation: generation 0, tag INIT_X, one word per coordinate. */
-void orc_init_population(const orc_problem *pb, int32_t np, uint32_t run_uid,
-                         uint64_t seed, double *X)
+void orc_restart_population(const orc_problem *pb, int32_t np, uint32_t run_uid, uint64_t seed, uint32_t k,
+                            double *X)
 {
     int D = pb->dim;
     uint32_t w[4];
     for (int i = 0; i < np; ++i)
         for (int j = 0; j < D; ++j) {
-            if (j % 4 == 0) draw(run_uid, seed, 0, (uint32_t)i, ORC_TAG_INIT_X, (uint32_t)(j / 4), 0, w);
+            if (j % 4 == 0) draw(run_uid, seed, 0, (uint32_t)i, ORC_TAG_INIT_X, (uint32_t)(j / 4), k, w);
             X[(size_t)i * D + j] = pb->lb + (pb->ub - pb->lb) * orc_u24(w[j % 4]);
         }
+}
+
+void orc_init_population(const orc_problem *pb, int32_t np, uint32_t run_uid,
+                         uint64_t seed, double *X)
+{
+    orc_restart_population(pb, np, run_uid, seed, 0, X);
 }
 
 /* Index in [0, n) with the members of `excl` (distinct, any order) skipped:
@@ -1077,6 +1083,17 @@ static void record(recorder *r, double e, const double *x)
     }
 }
 
+int orc_converged(const double *e, int32_t n, double tol)
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        const double k = key_of(e[i]);
+        if (k < lo) lo = k;
+        if (k > hi) hi = k;
+    }
+    return hi - lo <= tol;   /* false when an error is NaN or infinite */
+}
+
 /* Observer row g: (muF, muCR). */
 static void observe(double *mu, int64_t mu_len, int64_t g, double muF, double muCR)
 {
@@ -1110,7 +1127,7 @@ int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, o
     int D = d->dim, np = d->np;
     if (D < 1 || np < 1) return -1;
     if ((d->algo == ORC_ALGO_DE || d->algo == ORC_ALGO_SHADE || d->algo == ORC_ALGO_LSHADE ||
-         d->algo == ORC_ALGO_PSODE || d->algo == ORC_ALGO_JADE) && np < 4)
+         d->algo == ORC_ALGO_PSODE || d->algo == ORC_ALGO_JADE || d->algo == ORC_ALGO_LSHADE_RS) && np < 4)
         return -1;
     for (int64_t k = 0; mu && k < 2 * mu_len; ++k) mu[k] = NAN;
     orc_problem pb = { d->func, D, d->lb, d->ub };
@@ -1127,7 +1144,7 @@ int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, o
     for (int64_t k = 0; trace && k < trace_len; ++k) trace[k] = NAN;
 
     recorder rec = { 0, d->budget, INFINITY, INFINITY, trace, trace_len, best_x, D };
-    int gens = 0;
+    int gens = 0, restarts = 0;
     int rc = 0;
     if (d->algo == ORC_ALGO_PSO) {
         double *V = A, *P = B, *eP = eA;
@@ -1176,8 +1193,10 @@ int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, o
             if (d->algo == ORC_ALGO_DE) observe(mu, mu_len, gens, d->F, d->CR);
             else observe_memory(mu, mu_len, gens, H, MF, MCR);
         }
-    } else if (d->algo == ORC_ALGO_LSHADE || d->algo == ORC_ALGO_JADE) {
+    } else if (d->algo == ORC_ALGO_LSHADE || d->algo == ORC_ALGO_JADE || d->algo == ORC_ALGO_LSHADE_RS) {
         const int jade = d->algo == ORC_ALGO_JADE;
+        const int restart = d->algo == ORC_ALGO_LSHADE_RS;
+        int64_t fe_r = 0;   /* evaluations before the current restart */
         const int32_t np_min = jade ? np : d->np_min;
         if (np_min < 4 || np_min > np) { free(o); free(M); free(buf); return -1; }
         orc_lshade_state st;
@@ -1202,7 +1221,8 @@ int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, o
                 rc = orc_jade_generation(&pb, o, M, &st, d->p, d->r_arc, d->c, d->run_uid, seed,
                                          (uint32_t)gens, U, eU, NULL);
             } else {
-                const int32_t np_next = orc_lshade_np(np, np_min, d->budget, rec.fe + np_old);
+                /* the size schedule runs from the latest restart to the budget */
+                const int32_t np_next = orc_lshade_np(np, np_min, d->budget - fe_r, rec.fe - fe_r + np_old);
                 rc = orc_lshade_generation(&pb, o, M, &st, d->p, d->r_arc,
                                            np_next < np_old ? np_next : np_old, d->run_uid, seed,
                                            (uint32_t)gens, U, eU, NULL);
@@ -1210,6 +1230,19 @@ int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, o
             if (rc != 0) break;
             for (int i = 0; i < np_old; ++i) record(&rec, eU[i], U + (size_t)i * D);
             observe_memory(mu, mu_len, gens, st.H, st.MF, st.MCR);
+            if (restart && rec.fe < d->budget && orc_converged(st.eX, st.np, d->restart_tol)) {
+                /* a fresh population of np_init, memories at 0.5, an empty
+                   archive and the size schedule started over */
+                ++restarts;
+                fe_r = rec.fe;
+                st.np = np;
+                orc_restart_population(&pb, np, d->run_uid, seed, (uint32_t)restarts, X);
+                orc_error_aos(d->func, D, o, M, X, np, eX);
+                for (int i = 0; i < np; ++i) record(&rec, eX[i], X + (size_t)i * D);
+                for (int k = 0; k < st.H; ++k) { st.MF[k] = 0.5; st.MCR[k] = 0.5; }
+                st.pos = 0;
+                st.na = 0;
+            }
         }
         free(st.A);
     } else if (d->algo == ORC_ALGO_PSODE) {
@@ -1255,6 +1288,7 @@ int orc_run_observed(const orc_run_desc *d, uint64_t seed, uint64_t inst_seed, o
         res->fes = rec.fe;
         res->generations = gens;
         res->success = rec.best_budget <= 1e-8;
+        res->restarts = restarts;
     }
     free(o); free(M); free(buf);
     return rc;

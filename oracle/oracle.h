@@ -32,7 +32,7 @@ extern "C" {
 enum { ORC_ELLIPSOID = 0, ORC_ROSENBROCK = 1, ORC_RASTRIGIN = 2,
        ORC_SCHWEFEL = 3, ORC_GRIEWANK = 4, ORC_ACKLEY = 5, ORC_NFUNC = 6 };
 enum { ORC_ALGO_DE = 0, ORC_ALGO_PSO = 1, ORC_ALGO_SHADE = 2, ORC_ALGO_LSHADE = 3, ORC_ALGO_PSODE = 4,
-       ORC_ALGO_CSO = 5, ORC_ALGO_JADE = 6 };
+       ORC_ALGO_CSO = 5, ORC_ALGO_JADE = 6, ORC_ALGO_LSHADE_RS = 7 };
 
 /* Philox stream tags (third counter word, bits 24..31). */
 enum { ORC_TAG_INIT_X = 1, ORC_TAG_DONORS = 2, ORC_TAG_CROSS = 3,
@@ -77,6 +77,12 @@ void   orc_error_aos(int32_t func, int32_t dim, const double *o, const double *M
 double orc_error_z(int32_t func, int32_t dim, const double *z);
 
 /* ---- Differential evolution, rand/1/bin with midpoint-target repair ---- */
+/* Population of restart k: as orc_init_population with the last counter
+ * word k (k = 0 is the initial population). */
+void orc_restart_population(const orc_problem *pb, int32_t np, uint32_t run_uid, uint64_t seed, uint32_t k,
+                            double *X);
+/* 1 when max e - min e over e[0..n) <= tol (NaN counts as +infinity). */
+int orc_converged(const double *e, int32_t n, double tol);
 /* Population initialisation (generation 0): X[i*dim + j] = lb + (ub-lb) u24. */
 void orc_init_population(const orc_problem *pb, int32_t np, uint32_t run_uid,
                          uint64_t seed, double *X);
@@ -263,8 +269,20 @@ typedef struct {
     int32_t topology;      /* PSO: 0 global best, 1 ring */
     int32_t velocity;      /* PSO: 0 inertia weight, 1 spherical */
     double c;              /* JADE: adaptation rate of muF and muCR */
+    double restart_tol;    /* L-SHADE with restarts: convergence threshold */
 } orc_run_desc;
-/* JADE runs take p, r_arc (the archive bound per individual: 1 in JADE) and
+/* L-SHADE-Restart runs (ORC_ALGO_LSHADE_RS; the state-triggered restart
+ * that the paper's modular design makes, Sec. 4) are L-SHADE runs that,
+ * after a generation leaving budget, restart once the population has
+ * converged -- max e - min e over it <= restart_tol (orc_converged) --:
+ * restart k (1, 2, ...) draws a fresh population of np individuals
+ * (orc_restart_population with that k), evaluates and records it, resets
+ * the memories to 0.5 (pos = 0) and empties the archive, and the size
+ * schedule starts over: orc_lshade_np(np, np_min, budget - fe_r,
+ * fe - fe_r + np_current), fe_r the evaluations made before the restart.
+ * The generation counter keeps counting, and the best-so-far record spans
+ * all restarts.
+ * JADE runs take p, r_arc (the archive bound per individual: 1 in JADE) and
  * c; H and np_min are ignored (one parameter pair, no reduction).
  * CSO runs take np = m (even) and phi in c1; V starts at zero; an iteration
  * makes m/2 evaluations, recorded in pair order.
@@ -277,6 +295,7 @@ typedef struct {
     int64_t fes;           /* evaluations performed (whole generations) */
     int32_t generations;   /* generations after initialisation */
     int32_t success;       /* best_e <= 1e-8 */
+    int32_t restarts;      /* L-SHADE-Restart: restarts made */
 } orc_run_result;
 
 #define ORC_TRACE_EVERY 200

@@ -902,3 +902,83 @@ def test_observer_counts_a_terminal_cr_slot_as_zero():
         terminal += int(np.any(mcr < 0))
         assert mu[t] == pytest.approx([mf.mean(), np.where(mcr < 0, 0.0, mcr).mean()], rel=1e-15)
     assert terminal > 0
+
+
+# ------------------------------------------------------------------ L-SHADE with restarts
+
+def test_restart_population_k0_is_the_initial_population():
+    X0 = O.init_population(O.RASTRIGIN, 7, LB, UB, 30, 5, SEED)
+    assert np.array_equal(O.restart_population(O.RASTRIGIN, 7, LB, UB, 30, 5, SEED, 0), X0)
+    seen = [X0]
+    for k in (1, 2, 77):
+        Xk = O.restart_population(O.RASTRIGIN, 7, LB, UB, 30, 5, SEED, k)
+        assert np.all((Xk >= LB) & (Xk < UB))
+        assert all(not np.any(Xk == S) for S in seen)   # fresh draws, no shared coordinate
+        seen.append(Xk)
+
+
+def test_converged_spread():
+    assert O.converged([3.0, 3.0, 3.0], 0.0)
+    assert O.converged([1.0, 1.5], 0.5) and not O.converged([1.0, 1.5], 0.49)
+    assert not O.converged([1.0, np.nan], 1e300)
+    assert not O.converged([np.inf, np.inf], 1e300)
+
+
+def _rs_desc(func, D, np_, budget, tol, **kw):
+    return _desc(O.ALGO_LSHADE_RS, func, D, np_, budget, p=0.11, r_arc=1.4, np_min=4, restart_tol=tol, **kw)
+
+
+def test_lshade_restart_never_triggered_is_lshade():
+    func, D, np_, budget = O.SCHWEFEL, 6, 40, 4000
+    a = O.run(_rs_desc(func, D, np_, budget, -1.0), SEED, ISEED, trace_len=20, mu_len=200)
+    b = O.run(_desc(O.ALGO_LSHADE, func, D, np_, budget, p=0.11, r_arc=1.4, np_min=4), SEED, ISEED,
+              trace_len=20, mu_len=200)
+    assert a[0] == b[0] and a[0]["restarts"] == 0
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
+def _replay_restarts(func, D, np_, budget, tol, uid=1):
+    """The restart rule recomposed from the generation function: returns
+    (evaluations in order, generations, restarts, population sizes)."""
+    o, M = O.instance(func, D, 0, ISEED)
+    X = O.init_population(func, D, LB, UB, np_, uid, SEED)
+    eX = O.errors(func, o, M, X)
+    ls = O.LShade(func, D, LB, UB, o, M, X, eX, H=6, r_arc=1.4)
+    evals, fe, fe_r, t, k, sizes = list(eX), np_, 0, 0, 0, []
+    while fe < budget:
+        t += 1
+        n = ls.np
+        nn = min(O.lshade_np(np_, 4, budget - fe_r, fe - fe_r + n), n)
+        U, eU, _ = ls.generation(0.11, nn, uid, SEED, t)
+        evals += list(eU)
+        fe += n
+        sizes.append(n)
+        if fe < budget and O.converged(ls.eX[: ls.np], tol):
+            k += 1
+            fe_r = fe
+            X = O.restart_population(func, D, LB, UB, np_, uid, SEED, k)
+            eX = O.errors(func, o, M, X)
+            ls = O.LShade(func, D, LB, UB, o, M, X, eX, H=6, r_arc=1.4)
+            evals += list(eX)
+            fe += np_
+    return np.array(evals), t, k, sizes
+
+
+@pytest.mark.parametrize("func,tol", [(O.ELLIPSOID, 1e300), (O.ELLIPSOID, 1e-6), (O.RASTRIGIN, 1e-3),
+                                      (O.ROSENBROCK, 0.5)])
+def test_lshade_restart_run_matches_replay(func, tol):
+    """The run driver against the rule recomposed by hand: restart after a
+    generation that leaves budget and a converged population, a fresh
+    population k, memories and archive reset, the size schedule started
+    over; the best and the trace span all restarts."""
+    D, np_, budget = 4, 24, 24 * 250
+    res, trace, _ = O.run(_rs_desc(func, D, np_, budget, tol), SEED, ISEED, trace_len=budget // 200)
+    e, gens, k, sizes = _replay_restarts(func, D, np_, budget, tol)
+    assert res["fes"] == len(e) and res["generations"] == gens and res["restarts"] == k
+    assert res["best_e"] == e[:budget].min()
+    assert np.array_equal(trace, [e[: 200 * (j + 1)].min() for j in range(budget // 200)])
+    if tol > 1e100:
+        assert k == gens - 1 or k == gens          # a restart after every generation with budget left
+        assert all(s == np_ for s in sizes)          # the schedule never gets to shrink
+    assert k > 0                                     # every case here restarts at least once
