@@ -21,7 +21,7 @@
  *     record every 200 evaluations (Sec. 2.4, Sec. 3.2); also L-SHADE, the
  *     SHADE variant with an external archive and population size reduction
  *     that the DE module's archive and reduction mechanisms make (Sec. 2.2,
- *     and the L-SHADE family of Sec. 4);
+ *     and the L-SHADE family of Sec. 4), with restarts (L-SHADE-Restart);
  *   - sevo_run_observed: sevo_run with the suite observer that follows the
  *     adaptive parameters muF and muCR through each run (Sec. 4, second case
  *     study, Fig. 9), for JADE and the success-history family.
@@ -84,7 +84,7 @@ enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFE
 enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
 
 enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3, SEVO_ALGO_PSODE = 4,
-       SEVO_ALGO_CSO = 5, SEVO_ALGO_JADE = 6 };
+       SEVO_ALGO_CSO = 5, SEVO_ALGO_JADE = 6, SEVO_ALGO_LSHADE_RS = 7 };
 
 typedef struct sevo_ctx sevo_ctx;   /* opaque, library-owned */
 
@@ -263,6 +263,7 @@ typedef struct {
     int32_t velocity;      /* PSO, PSODE: 0 inertia weight, 1 spherical (SPSO-2011; FP32 runs) */
     int32_t reserved;      /* 0 */
     double c;              /* JADE: adaptation rate of muF and muCR, 0 .. 1 (0.1 in JADE) */
+    double restart_tol;    /* L-SHADE-Restart: restart once max e - min e over the population <= this */
 } sevo_run_desc;
 
 typedef struct {
@@ -272,7 +273,7 @@ typedef struct {
     int32_t success;       /* best_e <= 1e-8 */
     int64_t fes;           /* evaluations made (the last generation may overshoot) */
     int32_t generations;   /* generations after initialisation */
-    int32_t reserved;
+    int32_t restarts;      /* L-SHADE-Restart: restarts made (0 for the others) */
 } sevo_run_result;
 
 /* Run n_runs independent runs to their budgets in persistent fused kernels
@@ -304,6 +305,15 @@ typedef struct {
  *   move where strictly better than the DE result.  2 np evaluations per
  *   generation, recorded as the PSO moves, then the DE trials; velocities
  *   start at 0.
+ *   L-SHADE-Restart (SEVO_ALGO_LSHADE_RS; the state-triggered restart of
+ *   the case study's L-SHADE family, Sec. 4): L-SHADE that, after a
+ *   generation leaving budget, restarts once its population has converged
+ *   (max e - min e over it <= restart_tol; NaN counts as +infinity, so it
+ *   never converges): restart k = 1, 2, ... draws a fresh population of np
+ *   (the initial draws with the last Philox counter word k), evaluates and
+ *   records it, resets the memories to 0.5 and empties the archive, and the
+ *   size schedule starts over from np at that point to np_min at the
+ *   budget.  The best-so-far record spans all restarts.
  *   JADE (Zhang and Sanderson 2009; the algorithm of the parameter
  *   observer case study, Sec. 4; FP32 runs, np >= 4): L-SHADE's generation
  *   with one parameter pair (muF, muCR) in place of the memory (H is

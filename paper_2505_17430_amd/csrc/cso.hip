@@ -343,7 +343,7 @@ __global__ __launch_bounds__(CSO_THREADS) void k_cso_finish(const CsoDev *__rest
         o.success = e64 <= 1e-8 ? 1 : 0;
         o.fes = (int64_t)R.m + (int64_t)R.iters * R.h;
         o.generations = R.iters;
-        o.reserved = 0;
+        o.restarts = 0;
     }
     if (R.best_x_out)
         for (int j = threadIdx.x; j < R.dim; j += CSO_THREADS)

@@ -36,7 +36,7 @@ int32_t shade_pnum(double p, int32_t np)
 // population, plus one); 0 for the other algorithms.
 int archive_cap(const sevo_run_desc &d)
 {
-    if (d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_JADE) return 0;
+    if (d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_JADE && d.algo != SEVO_ALGO_LSHADE_RS) return 0;
     return (int)std::lround(d.r_arc * (double)d.np) + 1;
 }
 
@@ -54,7 +54,7 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             return set_error(ctx, SEVO_EINVAL, "run has an invalid problem");
         if (d.algo != SEVO_ALGO_DE && d.algo != SEVO_ALGO_PSO && d.algo != SEVO_ALGO_SHADE &&
             d.algo != SEVO_ALGO_LSHADE && d.algo != SEVO_ALGO_PSODE && d.algo != SEVO_ALGO_CSO &&
-            d.algo != SEVO_ALGO_JADE)
+            d.algo != SEVO_ALGO_JADE && d.algo != SEVO_ALGO_LSHADE_RS)
             return set_error(ctx, SEVO_EINVAL, "unknown algorithm");
         if (d.algo == SEVO_ALGO_CSO) {
             // CSO: the update kernels and the batched evaluation, any D
@@ -77,11 +77,14 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             return set_error(ctx, SEVO_EINVAL, "DE needs finite F and CR in [0, 1]");
         if (pso_like && !(d.vmax > 0))
             return set_error(ctx, SEVO_EINVAL, "PSO needs vmax > 0");
-        if ((d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE || d.algo == SEVO_ALGO_PSODE) &&
+        const bool lshade_like = d.algo == SEVO_ALGO_LSHADE || d.algo == SEVO_ALGO_LSHADE_RS;
+        if ((d.algo == SEVO_ALGO_SHADE || lshade_like || d.algo == SEVO_ALGO_PSODE) &&
             (d.H < 1 || d.H > 16 || !(d.p > 0 && d.p <= 1)))
             return set_error(ctx, SEVO_EINVAL, "SHADE needs H in [1, 16] and p in (0, 1]");
-        if (d.algo == SEVO_ALGO_LSHADE && (d.np_min < 4 || d.np_min > d.np || !(d.r_arc >= 0 && d.r_arc <= 2.9)))
+        if (lshade_like && (d.np_min < 4 || d.np_min > d.np || !(d.r_arc >= 0 && d.r_arc <= 2.9)))
             return set_error(ctx, SEVO_EINVAL, "L-SHADE needs np_min in [4, np] and r_arc in [0, 2.9]");
+        if (d.algo == SEVO_ALGO_LSHADE_RS && std::isnan(d.restart_tol))
+            return set_error(ctx, SEVO_EINVAL, "L-SHADE-Restart needs a restart_tol that is not NaN");
         if (d.algo == SEVO_ALGO_JADE &&
             (!(d.p > 0 && d.p <= 1) || !(d.r_arc >= 0 && d.r_arc <= 2.9) || !(d.c >= 0 && d.c <= 1)))
             return set_error(ctx, SEVO_EINVAL, "JADE needs p in (0, 1], r_arc in [0, 2.9] and c in [0, 1]");
@@ -92,7 +95,7 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             return set_error(ctx, SEVO_EINVAL, "PSO topology and velocity are 0 or 1");
         if (precision == SEVO_FP64 && d.algo == SEVO_ALGO_PSO && (d.topology != 0 || d.velocity != 0))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision PSO is global-best inertia");
-        if (precision == SEVO_FP64 && (d.algo == SEVO_ALGO_SHADE || d.algo == SEVO_ALGO_LSHADE ||
+        if (precision == SEVO_FP64 && (d.algo == SEVO_ALGO_SHADE || lshade_like ||
                                        d.algo == SEVO_ALGO_PSODE || d.algo == SEVO_ALGO_JADE))
             return set_error(ctx, SEVO_EUNSUPPORTED, "the double-precision run path has DE and PSO");
     }
@@ -233,6 +236,8 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.mu_len = mu_len;
         R.c_adapt = d.c;
         R.CR = (float)d.CR;
+        R.restart = d.algo == SEVO_ALGO_LSHADE_RS ? 1 : 0;
+        R.restart_tol = d.restart_tol;
         Group &G = groups[(ks_of(R.dim) * NFAM + family_of(d.algo)) * 4 + onchip[r] * 2 + wave[r]];
         G.runs.push_back(R);
         G.cost.push_back((double)d.budget * R.dim * R.dim);

@@ -67,6 +67,9 @@ struct RunDev {
     int64_t mu_len;
     double c_adapt;
     float CR;
+    // L-SHADE-Restart: restarts enabled, and the convergence threshold
+    int32_t restart;
+    double restart_tol;
 };
 
 // A team carries one run: the whole workgroup (256 threads, phases separated
@@ -384,7 +387,7 @@ inline int family_of(int algo)
 {
     return algo == SEVO_ALGO_PSO ? FAM_PSO
          : algo == SEVO_ALGO_SHADE ? FAM_SHADE
-         : algo == SEVO_ALGO_LSHADE || algo == SEVO_ALGO_JADE ? FAM_LSHADE
+         : algo == SEVO_ALGO_LSHADE || algo == SEVO_ALGO_JADE || algo == SEVO_ALGO_LSHADE_RS ? FAM_LSHADE
          : algo == SEVO_ALGO_PSODE ? FAM_PSODE
                                     : FAM_DE;
 }
@@ -488,25 +491,30 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     const int lane = t.lane, wave = t.wave;
     constexpr int NW = Team<WAVE>::NW;
 
-    // generation 0: x uniform in the box (double, then rounded to float)
-    for (int jb = wave; jb * 4 < D; jb += NW)
-        for (int i = lane; i < np; i += 64) {
-            const u32x4 w = draw(R.run_uid, seed32, 0, (uint32_t)i, TAG_INIT_X, (uint32_t)jb);
+    // population k: x uniform in the box (double, then rounded to float),
+    // k = 0 at generation 0, k >= 1 at L-SHADE-Restart's restarts
+    auto draw_population = [&](uint32_t k) {
+        for (int jb = wave; jb * 4 < D; jb += NW)
+            for (int i = lane; i < np; i += 64) {
+                const u32x4 w = draw(R.run_uid, seed32, 0, (uint32_t)i, TAG_INIT_X, (uint32_t)jb, k);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = jb * 4 + e;
-                if (j < D) {
-                    const float x = (float)((double)R.lb + ((double)R.ub - (double)R.lb) * u24d(word(w, e)));
-                    X[j * npp + i] = x;
-                    if (pso) { V[j * npp + i] = 0.f; P[j * npp + i] = x; }
-                    if (psode) V[j * npp + i] = 0.f;
+                for (int e = 0; e < 4; ++e) {
+                    const int j = jb * 4 + e;
+                    if (j < D) {
+                        const float x = (float)((double)R.lb + ((double)R.ub - (double)R.lb) * u24d(word(w, e)));
+                        X[j * npp + i] = x;
+                        if (pso) { V[j * npp + i] = 0.f; P[j * npp + i] = x; }
+                        if (psode) V[j * npp + i] = 0.f;
+                    }
                 }
             }
-        }
-    t.sync();
+        t.sync();
+    };
+    draw_population(0);
 
     int64_t fe = 0;
-    int gen = 0;
+    int64_t fe_r = 0;   // L-SHADE-Restart: evaluations before the latest restart
+    int gen = 0, restarts = 0;
     // recorder for the np evaluations eY (in index order) made at fe0
     auto record = [&](const float *Y, const float *eY) {
         float pv;
@@ -596,6 +604,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     while (fe < R.budget) {
         ++gen;
         const uint32_t tg = (uint32_t)gen;
+        int np_next = np;   // L-SHADE: the size after this generation
         if constexpr (moves) {
             // ---- PSO: update, evaluate, personal and global bests ----
             // (PSODE: the move goes to Y, its errors to sEP; the personal
@@ -883,8 +892,9 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
             observe(gen);
             if (psode && R.topology == 0) global_best(sEX);
             if (lshade) {
-                // linear population size reduction: the best nn stay, in index order
-                const int nn = min(lshade_np(R.np, R.np_min, R.budget, fe + np), np);
+                // linear population size reduction (from the latest restart to the
+                // budget): the best nn stay, in index order
+                const int nn = min(lshade_np(R.np, R.np_min, R.budget - fe_r, fe - fe_r + np), np);
                 if (nn < np) {
                     if (tid < np) {
                         const uint32_t bits = __float_as_uint(err_key(sEX[tid]));
@@ -930,13 +940,39 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                     }
                     if (tid == 0) sNaA[s] = na;
                     t.sync();
-                    fe += np;
-                    np = nn;
-                    continue;
+                    np_next = nn;
                 }
             }
         }
         fe += np;
+        np = np_next;
+        if (lshade && R.restart && fe < R.budget) {
+            // L-SHADE-Restart: restart once the population's errors span at
+            // most restart_tol (NaN counts as +infinity: never converged)
+            float pv;
+            int pi;
+            prefix_min(t, tid < np ? err_key(sEX[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
+            const float lo = sPv[TS - 1];
+            t.sync();
+            prefix_min(t, tid < np ? -err_key(sEX[tid]) : INFINITY, tid, sPv, sPi, sWv, sWi, pv, pi);
+            const float hi = -sPv[TS - 1];
+            t.sync();
+            if ((double)(hi - lo) <= R.restart_tol) {
+                // a fresh population, memories at 0.5, an empty archive, and
+                // the size schedule started over
+                ++restarts;
+                fe_r = fe;
+                np = R.np;
+                draw_population((uint32_t)restarts);
+                eval_pop<KS, ONCHIP>(t, R, np, X, sEX, sA, sO, sT, K);
+                t.sync();
+                record(X, sEX);
+                fe += np;
+                if (tid < 16) { sMF[tid] = 0.5f; sMCR[tid] = 0.5f; }
+                if (tid == 0) { sPosA[s] = 0; sNaA[s] = 0; }
+                t.sync();
+            }
+        }
     }
 
     // observer rows of generations not made (PSO: every row) are NaN
@@ -967,7 +1003,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
         o.success = e64 <= 1e-8 ? 1 : 0;
         o.fes = fe;
         o.generations = gen;
-        o.reserved = 0;
+        o.restarts = restarts;
     }
     if (R.best_x_out)
         for (int j = tid; j < D; j += TS) R.best_x_out[(int64_t)R.out_index * R.max_dim + j] = (double)R.bestx[j];

@@ -251,7 +251,7 @@ __global__ void k_run_finish(const RecState *rec, sevo_run_result *out, int64_t 
         out->success = rec->best_b <= 1e-8 ? 1 : 0;
         out->fes = fes;
         out->generations = gens;
-        out->reserved = 0;
+        out->restarts = 0;
     }
     if (best_x_out)
         for (int j = threadIdx.x; j < dim; j += blockDim.x) best_x_out[j] = bestx[j];

@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
 ELLIPSOID, ROSENBROCK, RASTRIGIN, SCHWEFEL, GRIEWANK, ACKLEY = range(6)
 FUNC_NAMES = ["ellipsoid", "rosenbrock", "rastrigin", "schwefel", "griewank", "ackley"]
 FP64, FP32, SPLIT_BF16 = 0, 1, 2
-ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO, ALGO_JADE = 0, 1, 2, 3, 4, 5, 6
+ALGO_DE, ALGO_PSO, ALGO_SHADE, ALGO_LSHADE, ALGO_PSODE, ALGO_CSO, ALGO_JADE, ALGO_LSHADE_RS = range(8)
 TRACE_EVERY = 200
 
 
@@ -72,12 +72,13 @@ class RunDesc(C.Structure):
                 ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
                 ("p", C.c_double), ("H", C.c_int32),
                 ("r_arc", C.c_double), ("np_min", C.c_int32), ("topology", C.c_int32),
-                ("velocity", C.c_int32), ("reserved", C.c_int32), ("c", C.c_double)]
+                ("velocity", C.c_int32), ("reserved", C.c_int32), ("c", C.c_double),
+                ("restart_tol", C.c_double)]
 
 
 class RunResult(C.Structure):
     _fields_ = [("best_e", C.c_double), ("best_e32", C.c_float), ("success", C.c_int32),
-                ("fes", C.c_int64), ("generations", C.c_int32), ("reserved", C.c_int32)]
+                ("fes", C.c_int64), ("generations", C.c_int32), ("restarts", C.c_int32)]
 
 
 def header_functions():
