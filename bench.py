@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--one-precision", action="store_true",
+                    help="c2: time only --precision (default: also the other single precision, reported beside)")
     ap.add_argument("--workload", default="c2",
                     choices=["c1", "c2", "c3", "c4", "c5", "lshade", "psode", "cso", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
@@ -166,54 +168,73 @@ def main():
     torch.cuda.synchronize()
     n_evals = sum(g[3] for g in groups)
     bytes_in = sum(g[3] * (4 * g[1] + 4) for g in groups)
-    # launch shapes chosen by the library's autotuner on the first replica
-    # (setup, outside the timed region; the choice does not change results)
-    tuned = {}
-    if not a.no_tune:
-        for d in W.C2_DIMS:
-            tuned.update(ctx.tune_evaluate(reps[0][d][1], precision=prec, stream=stream))
+    def timed(prec):
+        """Time a.steps steps of the sweep in one precision; returns
+        (ms per step, mean D=100 launch ms, tuned launch shapes)."""
+        # launch shapes chosen by the library's autotuner on the first replica
+        # (setup, outside the timed region; the choice does not change results)
+        tuned = {}
+        if not a.no_tune:
+            for d in W.C2_DIMS:
+                tuned.update(ctx.tune_evaluate(reps[0][d][1], precision=prec, stream=stream))
 
-    def step(rep, ev=None):
-        for d in W.C2_DIMS:
-            if ev is not None and d == 100:
-                ev[0].record(stream)
-            ctx.evaluate_batch(rep[d][1], precision=prec, stream=stream)
-            if ev is not None and d == 100:
-                ev[1].record(stream)
+        def step(rep, ev=None):
+            for d in W.C2_DIMS:
+                if ev is not None and d == 100:
+                    ev[0].record(stream)
+                ctx.evaluate_batch(rep[d][1], precision=prec, stream=stream)
+                if ev is not None and d == 100:
+                    ev[1].record(stream)
 
-    for w in range(a.warmup):
-        step(reps[w % a.replicas])
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(a.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for s in range(a.steps):
-        step(reps[s % a.replicas], evs[s])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ctx.sync(stream)
-    ms = t_start.elapsed_time(t_end)
-    ms_step = ms / a.steps
-    value = n_evals * a.steps / (ms / 1e3)
-    d100_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        for w in range(a.warmup):
+            step(reps[w % a.replicas])
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(a.steps)]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for s in range(a.steps):
+            step(reps[s % a.replicas], evs[s])
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        ctx.sync(stream)
+        return (t_start.elapsed_time(t_end) / a.steps,
+                float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])), tuned)
+
     n100 = sum(g[3] for g in by_dim[100])
     flops100 = 2.0 * 100 * 100 * n100
+    ms_step, d100_ms, tuned = timed(prec)
+    value = n_evals / (ms_step / 1e3)
+    legs = {}
+    if not a.one_precision:
+        # the other single precision, reported beside (each meets the
+        # evaluation tolerance in the parity tests)
+        other = S.SPLIT_BF16 if prec == S.FP32 else S.FP32
+        o_ms, o_d100, o_tuned = timed(other)
+        for name, pr, ms_, d_ in ((a.precision, prec, ms_step, d100_ms),
+                                  ("bf16" if other == S.SPLIT_BF16 else "fp32", other, o_ms, o_d100)):
+            legs["split_bf16" if name == "bf16" else "fp32"] = {
+                "ms_per_step": round(ms_, 4), "evals_per_s": round(n_evals / (ms_ / 1e3), 1),
+                "d100_kernel_ms": round(d_, 4),
+                "d100_tflops_fp32_equiv": round(flops100 / (d_ / 1e3) / 1e12, 3)}
+    achieved = flops100 / (d100_ms / 1e3) / 1e12
     if prec == S.FP32:
-        achieved = flops100 / (d100_ms / 1e3) / 1e12
-        peak = PEAK_FP32_MFMA_TFLOPS
-    else:   # small D runs the FP32 MFMA path in either precision
-        achieved = flops100 / (d100_ms / 1e3) / 1e12
-        peak = PEAK_FP32_MFMA_TFLOPS
-    traffic = measured_traffic()
+        peak, kname = PEAK_FP32_MFMA_TFLOPS, "k_eval_small<25> (D=100 group: 60 items x 5100 points)"
+    else:
+        # D = 100 runs k_eval_small_bf16<25>: 96 of the 100 coordinates in
+        # six bf16 products on the bf16 MFMA, counted against its own peak
+        # (the other 4 run on the float MFMA and are not counted)
+        achieved *= 6 * 96 / 100
+        peak, kname = PEAK_BF16_MFMA_TFLOPS, "k_eval_small_bf16<25> (D=100 group: 60 items x 5100 points)"
+    traffic = measured_traffic() if prec == S.FP32 else None
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": None if traffic is None else int(traffic),
             "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
             "algorithmic_bytes": int(n100 * (4 * 100 + 4)),
-            "kernel": "k_eval_small<25> (D=100 group: 60 items x 5100 points)",
+            "kernel": kname,
             "kernel_ms": round(d100_ms, 4)}
     out = {
         "metric": "function evals/sec, batched FP32/split-BF16 vs plain FP64, at stated rel. error",
@@ -226,17 +247,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == S.FP32 else "bf16x6",
         "data": "synthetic",
         "config": {"workload": "batched evaluation: 6 functions x D in {10,30,50,100} x 10 "
-                               "instances x 51 runs x 100 points, shifted-rotated, FP32 MFMA "
-                               "rotation, compensated FP32 objective",
+                               "instances x 51 runs x 100 points, shifted-rotated, "
+                               + ("FP32 MFMA rotation" if prec == S.FP32 else
+                                  "split-bf16 rotation (three-term split, six bf16 products) for D=100, "
+                                  "FP32 MFMA below")
+                               + ", compensated FP32 objective",
                    "evals_per_step": n_evals, "input_bytes_per_step": bytes_in,
                    "replicas": a.replicas, "precision": a.precision,
                    "tiles_per_workgroup": {str(k): v for k, v in sorted(tuned.items())} or "resident grid",
                    "tolerance": "|de| <= max(1e-6, 1e-5 e) vs FP64 oracle"},
         "roofline": roof,
     }
+    if legs:
+        out["precisions"] = legs
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     ctx.close()

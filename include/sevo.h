@@ -78,9 +78,13 @@ enum { SEVO_ELLIPSOID = 0, SEVO_ROSENBROCK = 1, SEVO_RASTRIGIN = 2, SEVO_SCHWEFE
 
 /* Arithmetic of the evaluation.  FP32: FP64 shift, FP32 rotation on matrix
  * cores, compensated FP32 reduction; state and errors are float.
- * SPLIT_BF16: as FP32 but the rotation is three bf16 products (hi*hi +
- * hi*lo + lo*hi) with FP32 accumulation.  FP64: everything in double;
- * state and errors are double. */
+ * SPLIT_BF16: as FP32 but the rotation runs on the bf16 matrix cores with
+ * FP32 accumulation: for D > 120 each float is split into two bf16 terms
+ * and three products are kept (hi*hi + hi*lo + lo*hi); for 65 <= D <= 112
+ * into three terms with the six products down to order 2^-16, the
+ * coordinates past the last multiple of 32 on the FP32 matrix cores; other
+ * D as FP32.  Both meet the evaluation tolerance.  FP64: everything in
+ * double; state and errors are double. */
 enum { SEVO_FP64 = 0, SEVO_FP32 = 1, SEVO_SPLIT_BF16 = 2 };
 
 enum { SEVO_ALGO_DE = 0, SEVO_ALGO_PSO = 1, SEVO_ALGO_SHADE = 2, SEVO_ALGO_LSHADE = 3, SEVO_ALGO_PSODE = 4,

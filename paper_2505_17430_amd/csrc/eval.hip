@@ -98,6 +98,77 @@ __global__ __launch_bounds__(256, CT == 1 ? 3 : 2) void k_eval_small(const EvalD
     }
 }
 
+// The split-bf16 evaluation of D = 65 .. 112: the same persistent grid, loads
+// and objective as k_eval_small, with the rotation's whole 32-coordinate
+// steps as six bf16 products on v_mfma_f32_16x16x32_bf16 and the rest on the
+// float MFMA.  The three bf16 terms of M and the remaining float fragments
+// take up to 71 KB of dynamic LDS (Bf16Steps::LDS_BYTES), two workgroups
+// per CU.
+template <int KS, int CT>
+__global__ __launch_bounds__(256, 2) void k_eval_small_bf16(const EvalDesc *__restrict__ items, int n_items,
+                                                            int total_tiles, int grid, Consts K)
+{
+    constexpr int RT = Bf16Steps<KS>::RT, SF = Bf16Steps<KS>::SF;
+    constexpr int TILE = 64 * CT;
+    extern __shared__ __attribute__((aligned(16))) bf16x8 sAb[];
+    float *sAr = reinterpret_cast<float *>(sAb + Bf16Steps<KS>::NVEC);
+    __shared__ double sO[KS * 4];
+    __shared__ float sT[RT * 16];
+
+    const int L = xcd_remap(blockIdx.x, grid);
+    const int tb = (int)(((int64_t)L * total_tiles) / grid);
+    const int te = (int)(((int64_t)(L + 1) * total_tiles) / grid);
+    if (tb >= te) return;
+    const int32_t *__restrict__ tile_item = reinterpret_cast<const int32_t *>(items + n_items);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, pc = lane & 15;
+
+    int cur = -1;
+    const EvalDesc *it = nullptr;
+    float b[KS][CT], bn[KS][CT];
+    bool have_next = false;
+    for (int g = tb; g < te; ++g) {
+        const int item = tile_item[g];
+        if (item != cur) {
+            __syncthreads();   // every wave is done with the previous item's LDS
+            cur = item;
+            it = items + item;
+            const SEVO_GLOBAL double *og = gin<double>(it->o);
+            const SEVO_GLOBAL float *tg = gin<float>(it->tab);
+            stage_rotation_bf16<KS>(sAb, sAr, it->Mbf, it->Mfrag);
+            for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
+            for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
+            __syncthreads();
+            have_next = false;
+        }
+        const int dim = it->dim, n = it->n;
+        const int64_t ld = it->ld;
+        const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
+        SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
+        const int p0 = (g - it->block0) * TILE + wave * 16 * CT;
+        if (have_next) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) b[ks][c] = bn[ks][c];
+        } else {
+            load_b<KS, CT>(b, X, ld, dim, n, p0, kq, pc, sO);
+        }
+        have_next = g + 1 < te && tile_item[g + 1] == item;
+        if (have_next) load_b<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc, sO);
+        bf16x8 bt[3][SF][CT];
+        split3_b<KS, CT>(bt, b);
+        switch (it->func) {
+        case ELLIPSOID: tile_body_bf16<ELLIPSOID, KS, CT>(bt, b, sAb, sAr, sT, lane, dim, n, p0, K.kf, E); break;
+        case ROSENBROCK: tile_body_bf16<ROSENBROCK, KS, CT>(bt, b, sAb, sAr, sT, lane, dim, n, p0, K.kf, E); break;
+        case RASTRIGIN: tile_body_bf16<RASTRIGIN, KS, CT>(bt, b, sAb, sAr, sT, lane, dim, n, p0, K.kf, E); break;
+        case SCHWEFEL: tile_body_bf16<SCHWEFEL, KS, CT>(bt, b, sAb, sAr, sT, lane, dim, n, p0, K.kf, E); break;
+        case GRIEWANK: tile_body_bf16<GRIEWANK, KS, CT>(bt, b, sAb, sAr, sT, lane, dim, n, p0, K.kf, E); break;
+        default: tile_body_bf16<ACKLEY, KS, CT>(bt, b, sAb, sAr, sT, lane, dim, n, p0, K.kf, E); break;
+        }
+    }
+}
+
 // Points per wave: two 16-point column tiles while the coordinates fit
 // comfortably in registers, one for the larger dimensions.
 #ifndef SEVO_CT_LARGE
@@ -105,17 +176,54 @@ __global__ __launch_bounds__(256, CT == 1 ? 3 : 2) void k_eval_small(const EvalD
 #endif
 constexpr int ct_for(int ks) { return ks <= 8 ? 2 : SEVO_CT_LARGE; }
 
-int small_tile_points(int ks) { return 64 * ct_for(ks); }
+// Split bf16: column tiles per wave (two halve the LDS traffic of the
+// fragments per MFMA).
+#ifndef SEVO_CT_BF16
+#define SEVO_CT_BF16 2
+#endif
+constexpr int ct_for_bf16(int ks) { return ks <= 8 ? 2 : SEVO_CT_BF16; }
+
+int small_tile_points(int ks, bool bf16) { return 64 * (bf16 ? ct_for_bf16(ks) : ct_for(ks)); }
+
+bool small_bf16_class(int ks) { return ks >= SMALL_BF16_KS_MIN && ks <= SMALL_BF16_KS_MAX; }
 
 typedef void (*SmallKernel)(const EvalDesc *, int, int, int, Consts);
 
 template <int KS>
-static SmallKernel small_kernel() { return k_eval_small<KS, ct_for(KS)>; }
+static SmallKernel small_kernel(bool bf16)
+{
+    if constexpr (KS >= SMALL_BF16_KS_MIN && KS <= SMALL_BF16_KS_MAX)
+        if (bf16) return k_eval_small_bf16<KS, ct_for_bf16(KS)>;
+    return bf16 ? nullptr : k_eval_small<KS, ct_for(KS)>;
+}
 
-static SmallKernel small_table(int ks)
+template <int KS>
+static constexpr int small_dyn_lds_of() { return Bf16Steps<KS>::LDS_BYTES; }
+
+// Dynamic LDS of a launch (the split-bf16 kernel's fragments; 0 for the
+// float kernel).
+static int small_dyn_lds(int ks, bool bf16)
+{
+    if (!bf16 || !small_bf16_class(ks)) return 0;
+    switch (ks) {
+#define SEVO_KS_CASE(v) case v: return small_dyn_lds_of<v>();
+        SEVO_KS_CASE(9) SEVO_KS_CASE(10) SEVO_KS_CASE(11) SEVO_KS_CASE(12) SEVO_KS_CASE(13)
+        SEVO_KS_CASE(14) SEVO_KS_CASE(15) SEVO_KS_CASE(16) SEVO_KS_CASE(17) SEVO_KS_CASE(18)
+        SEVO_KS_CASE(19) SEVO_KS_CASE(20) SEVO_KS_CASE(21) SEVO_KS_CASE(22) SEVO_KS_CASE(23)
+        SEVO_KS_CASE(24) SEVO_KS_CASE(25) SEVO_KS_CASE(26) SEVO_KS_CASE(27) SEVO_KS_CASE(28)
+#undef SEVO_KS_CASE
+    default: return 0;
+    }
+}
+
+// The kernel of a launch, with its dynamic-LDS allowance raised once (above
+// the default 64 KB where needed); nullptr if unavailable.
+static SmallKernel small_ready(int ks, bool bf16);
+
+static SmallKernel small_table(int ks, bool bf16)
 {
     switch (ks) {
-#define SEVO_KS_CASE(v) case v: return small_kernel<v>();
+#define SEVO_KS_CASE(v) case v: return small_kernel<v>(bf16);
         SEVO_KS_CASE(1) SEVO_KS_CASE(2) SEVO_KS_CASE(3) SEVO_KS_CASE(4) SEVO_KS_CASE(5)
         SEVO_KS_CASE(6) SEVO_KS_CASE(7) SEVO_KS_CASE(8) SEVO_KS_CASE(9) SEVO_KS_CASE(10)
         SEVO_KS_CASE(11) SEVO_KS_CASE(12) SEVO_KS_CASE(13) SEVO_KS_CASE(14) SEVO_KS_CASE(15)
@@ -127,24 +235,40 @@ static SmallKernel small_table(int ks)
     }
 }
 
-int small_resident_blocks(int ks)
+static SmallKernel small_ready(int ks, bool bf16)
 {
-    SmallKernel k = small_table(ks);
+    static int done[64] = {};   // split-bf16 kernels: 1 once the attribute is set, -1 if refused
+    SmallKernel k = small_table(ks, bf16);
+    if (!k || !bf16 || ks < 0 || ks >= 64) return k;
+    if (!done[ks]) {
+        done[ks] = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       small_dyn_lds(ks, true)) == hipSuccess ? 1 : -1;
+        (void)hipGetLastError();
+    }
+    return done[ks] > 0 ? k : nullptr;
+}
+
+int small_resident_blocks(int ks, bool bf16)
+{
+    SmallKernel k = small_ready(ks, bf16);
     if (!k) return 1;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, small_dyn_lds(ks, bf16)) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     return per_cu * cus;
 }
 
 hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_tiles, int grid,
-                             const Consts &k, hipStream_t s)
+                             bool bf16, const Consts &k, hipStream_t s)
 {
-    SmallKernel kern = small_table(ks);
+    SmallKernel kern = small_ready(ks, bf16);
     if (!kern) return hipErrorInvalidValue;
     if (total_tiles <= 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, d_items, n_items, total_tiles, grid, k);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), small_dyn_lds(ks, bf16), s, d_items, n_items, total_tiles,
+                       grid, k);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ struct EvalDesc {
     const float *Mfrag;     // [RT][KS][64] MFMA A-operand fragments of M (float)
     const float *tab;       // [RT * 16] per-row table (ellipsoid weight, 1/sqrt(i))
     const double *M64;      // [dim][dim] row-major
-    const uint16_t *Mbf;    // bf16 hi block then lo block, each [RT][KS32][64][8]
+    const uint16_t *Mbf;    // bf16 term blocks: D > 120 hi, lo [RT][KS32][64][8] in natural column
+                            // order; D <= 120 hi, mid, lo [RT][KS / 8][64][8] in the small path's order
     float *part;            // large-D partial sums [RB][n][8] (workspace)
     void *opnd;             // large-D GEMM operands, 4 npad kpad bytes (workspace; layout at launch_eval_operands)
     int64_t ld;
@@ -65,12 +66,21 @@ inline int rt_of(int dim) { return (dim + 15) / 16; }
 inline int ks32_of(int dim) { return (dim + 31) / 32; }
 
 // eval.hip
-int small_tile_points(int ks);            // points per workgroup tile
-int small_resident_blocks(int ks);        // workgroups the whole GPU holds at once
+// Split bf16 runs the small path's rotation on bf16 MFMA for these k-step
+// classes (D = 65 .. 112).  Below, the float kernel serves both precisions:
+// measured at D = 50 the split was slower (59-64 us against 56 us per
+// 306,000 evaluations; the kernels are bound by vector work, which the
+// split adds to) and at D <= 30 the work is bound by memory.  Above 112
+// the fragments would leave room for one workgroup per CU only.
+constexpr int SMALL_BF16_KS_MIN = 17;
+constexpr int SMALL_BF16_KS_MAX = 28;
+bool small_bf16_class(int ks);
+int small_tile_points(int ks, bool bf16);            // points per workgroup tile
+int small_resident_blocks(int ks, bool bf16);        // workgroups the whole GPU holds at once
 // d_items: descriptors (block0 = first tile, nblocks = tiles of the item)
 // followed by the tile -> item map.
 hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int total_tiles, int grid,
-                             const Consts &k, hipStream_t s);
+                             bool bf16, const Consts &k, hipStream_t s);
 
 constexpr int LARGE_ROWS = 128;          // rows of z per workgroup (4 waves x 32)
 constexpr int LARGE_POINTS = 128;        // points per workgroup

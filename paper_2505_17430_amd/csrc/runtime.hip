@@ -150,7 +150,8 @@ struct sevo_ctx {
     int last_slot = -1;
     Consts consts;
     int tiles_per_block = 0;     // SEVO_TILES_PER_BLOCK override; 0 = none
-    int tuned_tpb[64] = {};      // sevo_tune_evaluate's choice per k-step class; 0 = resident grid
+    int tuned_tpb[2][64] = {};   // sevo_tune_evaluate's choice per (float / split-bf16 kernel, k-step
+                                 // class); 0 = resident grid
     sevo::Workspace ws;
     sevo_plan *rec = nullptr;           // plan being built (calls record instead of launching)
     std::vector<hipStream_t> streams;   // internal, default priority
@@ -229,11 +230,14 @@ int upload_instance(sevo_ctx *ctx, DevInstance &I)
         if (I.func == ELLIPSOID) tab[r] = (float)std::pow(10.0, 6.0 * r / (double)(D - 1));
         else if (I.func == GRIEWANK) tab[r] = (float)(1.0 / (2.0 * M_PI * std::sqrt((double)(r + 1))));
     }
-    // bf16 hi/lo split of each float of M in the A-operand order of the
-    // 16x16x32 bf16 MFMA (lane l holds row l % 16, columns 8 (l / 16) + 0..7):
-    // hi block [RT][K32][64][8] followed by the lo block.
-    const size_t half = (size_t)RT * K32 * 64 * 8;
-    std::vector<uint16_t> bf(2 * half, 0);
+    // bf16 terms of each float of M in the A-operand order of the 16x16x32
+    // bf16 MFMA (lane l holds row l % 16 and eight k-slots 8 (l / 16) + e),
+    // term blocks [RT][steps][64][8] one after another.
+    // D > 120 (the tiled GEMM): hi, lo; step kk, slot e is column
+    // 32 kk + 8 (l / 16) + e.
+    // D <= 120 (the small path): hi, mid, lo over the KS / 8 whole steps;
+    // step s, slot e is column 4 (8 s + e) + l / 16, the column the float
+    // path's k-step 8 s + e gives lane group l / 16.
     auto to_bf16 = [](float f) -> uint16_t {     // round to nearest even
         uint32_t u;
         std::memcpy(&u, &f, 4);
@@ -246,17 +250,25 @@ int upload_instance(sevo_ctx *ctx, DevInstance &I)
         std::memcpy(&f, &u, 4);
         return f;
     };
+    const bool small = D <= SMALL_D_MAX;
+    const int terms = small ? 3 : 2;
+    const int steps = small ? KS / 8 : K32;
+    const size_t block = (size_t)RT * steps * 64 * 8;
+    std::vector<uint16_t> bf(std::max<size_t>(terms * block, 8), 0);
     for (int rt = 0; rt < RT; ++rt)
-        for (int kk = 0; kk < K32; ++kk)
+        for (int kk = 0; kk < steps; ++kk)
             for (int l = 0; l < 64; ++l)
                 for (int e = 0; e < 8; ++e) {
-                    const int r = rt * 16 + (l & 15), c = kk * 32 + (l >> 4) * 8 + e;
+                    const int r = rt * 16 + (l & 15);
+                    const int c = small ? 4 * (8 * kk + e) + (l >> 4) : kk * 32 + (l >> 4) * 8 + e;
                     float f = 0.f;
                     if (r < D && c < D) f = (float)I.M[(size_t)r * D + c];
-                    const uint16_t hi = to_bf16(f);
-                    const size_t at = (((size_t)rt * K32 + kk) * 64 + l) * 8 + e;
-                    bf[at] = hi;
-                    bf[half + at] = to_bf16(f - from_bf16(hi));
+                    const size_t at = (((size_t)rt * steps + kk) * 64 + l) * 8 + e;
+                    for (int t = 0; t < terms; ++t) {
+                        const uint16_t h = to_bf16(f);
+                        bf[t * block + at] = h;
+                        f -= from_bf16(h);   // exact
+                    }
                 }
     HIP_TRY(ctx, hipMalloc(&I.d_o, sizeof(double) * D));
     HIP_TRY(ctx, hipMalloc(&I.d_M64, sizeof(double) * (size_t)D * D));
@@ -356,13 +368,15 @@ int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
 // Workgroups of a small-D launch: as many as the GPU holds at once, or
 // tiles / tpb for a tiles-per-workgroup choice (the SEVO_TILES_PER_BLOCK
 // override, else the autotuner's), never more than there are tiles.
-int small_grid(sevo_ctx *ctx, int ks, int tiles)
+int small_grid(sevo_ctx *ctx, int ks, bool bf16, int tiles)
 {
     static std::map<int, int> resident;
-    auto itr = resident.find(ks);
-    if (itr == resident.end()) itr = resident.emplace(ks, small_resident_blocks(ks)).first;
+    const int key = ks * 2 + (bf16 ? 1 : 0);
+    auto itr = resident.find(key);
+    if (itr == resident.end()) itr = resident.emplace(key, small_resident_blocks(ks, bf16)).first;
     long g = itr->second;
-    const int tpb = ctx->tiles_per_block > 0 ? ctx->tiles_per_block : (ks < 64 ? ctx->tuned_tpb[ks] : 0);
+    const int tpb =
+        ctx->tiles_per_block > 0 ? ctx->tiles_per_block : (ks < 64 ? ctx->tuned_tpb[bf16 ? 1 : 0][ks] : 0);
     if (tpb > 0) g = (tiles + tpb - 1) / tpb;
     return (int)std::max<long>(1, std::min<long>(g, tiles));
 }
@@ -422,15 +436,17 @@ int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision
     // the classes concurrently on internal streams was slower)
     for (auto &kv : small) {
         std::vector<EvalDesc> &v = kv.second;
-        const int ks = kv.first, tp = small_tile_points(ks);
+        const int ks = kv.first;
+        const bool bf16 = precision == SEVO_SPLIT_BF16 && small_bf16_class(ks);
+        const int tp = small_tile_points(ks, bf16);
         int tiles = 0;
         for (auto &d : v) {
             d.block0 = tiles;                       // first tile of the item
             d.nblocks = (d.n + tp - 1) / tp;        // tiles of the item
             tiles += d.nblocks;
         }
-        const int grid = small_grid(ctx, ks, tiles);
-        out.push_back({Launch{L_SMALL, nullptr, (int)v.size(), ks, tiles, grid, false, false, 0, 0, 0},
+        const int grid = small_grid(ctx, ks, bf16, tiles);
+        out.push_back({Launch{L_SMALL, nullptr, (int)v.size(), ks, tiles, grid, bf16, false, 0, 0, 0},
                        table_blob(v)});
     }
     if (!f64.empty()) {
@@ -638,7 +654,7 @@ static hipError_t exec_launch(sevo_ctx *ctx, const sevo::Launch &L, hipStream_t 
     using namespace sevo;
     switch (L.kind) {
     case L_SMALL:
-        return launch_eval_small((const EvalDesc *)L.d, L.n, L.ks, L.total, L.grid, ctx->consts, s);
+        return launch_eval_small((const EvalDesc *)L.d, L.n, L.ks, L.total, L.grid, L.flag, ctx->consts, s);
     case L_F64: return launch_eval_f64((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
     case L_LARGE: return launch_eval_large((const EvalDesc *)L.d, L.n, L.total, L.flag, ctx->consts, s);
     case L_COMBINE: return launch_eval_large_combine((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
@@ -906,10 +922,12 @@ int sevo_tune_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_ite
     const int cand[] = {0, 1, 2, 3, 4, 6, 8};
     for (auto &kv : by_ks) {
         const int ks = kv.first;
+        // the table of the kernel this precision runs for the class
+        int *tuned = &ctx->tuned_tpb[precision == SEVO_SPLIT_BF16 && small_bf16_class(ks) ? 1 : 0][ks];
         float best = 0.f;
         int best_tpb = 0;
         for (int c : cand) {
-            ctx->tuned_tpb[ks] = c;
+            *tuned = c;
             if ((rc = eval_items(ctx, kv.second, precision, st))) break;   // warm-up
             float ms_min = 0.f;
             for (int rep = 0; rep < 3 && !rc; ++rep) {
@@ -925,7 +943,7 @@ int sevo_tune_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_ite
             if (c == cand[0] || ms_min < best) { best = ms_min; best_tpb = c; }
         }
         if (rc) break;
-        ctx->tuned_tpb[ks] = best_tpb;
+        *tuned = best_tpb;
         if (chosen) chosen[ks] = best_tpb;
     }
     ctx->tiles_per_block = saved_override;

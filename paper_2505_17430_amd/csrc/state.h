@@ -42,7 +42,7 @@ struct Launch {
     int kind;
     const void *d;      // device descriptors
     int n, ks, total, grid;
-    bool flag;          // L_LARGE, L_OPERANDS: split bf16; L_RUN: population on chip
+    bool flag;          // L_SMALL, L_LARGE, L_OPERANDS: split bf16; L_RUN: population on chip
     bool wave;          // L_RUN: wave teams
     size_t shm;         // L_RUN: dynamic LDS bytes
     int stride;         // L_RUN: floats of dynamic LDS per run

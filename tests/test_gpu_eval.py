@@ -113,7 +113,10 @@ def test_parity_fp32(ctx, dim):
             check_f32(gpu_eval(ctx, func, dim, inst, X), func, o, M, X, eo, f"fp32 f{func} D{dim} i{inst}")
 
 
-@pytest.mark.parametrize("dim", [121, 200, 1000])
+# 65 .. 112: the small path's split-bf16 kernel (65 and 112 its ends; 96
+# whole bf16 steps only, 100 a float k-step after them); 33 .. 64 and
+# 113 .. 120: the float kernel serves the precision; above 120 the tiled GEMM
+@pytest.mark.parametrize("dim", [33, 50, 64, 65, 96, 100, 112, 113, 121, 200, 1000])
 def test_parity_split_bf16(ctx, dim):
     for func in range(6):
         o, M, X = _points(func, dim, 1, n=150)
@@ -229,11 +232,12 @@ def test_invalid_arguments(ctx):
     ctx.sync()
 
 
-def test_c2_full_size_sampled(ctx):
+@pytest.mark.parametrize("precision", [S.FP32, S.SPLIT_BF16])
+def test_c2_full_size_sampled(ctx, precision):
     """The full batched-evaluation workload (6 functions x D in {10,30,50,100}
     x 10 instances x 51 runs x 100 points) in one batch call, in the launch
-    configuration the benchmark times; a seeded sample of points per group is
-    checked one by one against the oracle."""
+    configuration the benchmark times, in both single precisions; a seeded
+    sample of points per group is checked one by one against the oracle."""
     groups = W.c2_groups()
     items, keep = [], []
     for (f, d, k, n) in groups:
@@ -242,8 +246,8 @@ def test_c2_full_size_sampled(ctx):
         e = torch.full((n,), float("nan"), device="cuda")
         items.append((S.problem(f, d), k, xd, e))
         keep.append((f, d, k, X, e))
-    say("  c2 items", len(items))
-    ctx.evaluate_batch(items)
+    say("  c2 items", len(items), "precision", precision)
+    ctx.evaluate_batch(items, precision=precision)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
     for (f, d, k, X, e) in keep:
