@@ -79,9 +79,11 @@ def parse():
     ap.add_argument("--one-precision", action="store_true",
                     help="c2: time only --precision (default: also the other single precision, reported beside)")
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "psode", "cso", "copy"],
+                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "lshade_rs", "jade", "psode", "cso", "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
                          "c4: batched SHADE; c5: D=1000 evaluation; lshade: the c4 runs as L-SHADE; "
+                         "lshade_rs: the c4 runs as L-SHADE-Restart; jade: the c4 runs as JADE with the "
+                         "muF/muCR observer; "
                          "psode: the case study's PSO/DE hybrid, batched; "
                          "cso: the large-scale study's CSO runs at D=1000; "
                          "copy: 512 MiB device copy "
@@ -282,8 +284,11 @@ def _line(metric, value, unit, steps, warmup, ms, config, dtype="f32", **extra):
     print(json.dumps(out), flush=True)
 
 
-_ALGO_PSODE = 4   # SEVO_ALGO_PSODE
-_ALGO_CSO = 5     # SEVO_ALGO_CSO
+_ALGO_LSHADE = 3      # SEVO_ALGO_LSHADE
+_ALGO_PSODE = 4       # SEVO_ALGO_PSODE
+_ALGO_CSO = 5         # SEVO_ALGO_CSO
+_ALGO_JADE = 6        # SEVO_ALGO_JADE
+_ALGO_LSHADE_RS = 7   # SEVO_ALGO_LSHADE_RS
 # SPSO-2011 constants of the spherical update: w = 1 / (2 ln 2), c = 1/2 + ln 2
 W_SPSO, C_SPSO = 1.0 / (2.0 * math.log(2.0)), 0.5 + math.log(2.0)
 
@@ -299,16 +304,35 @@ def _pso_settings(spec):
     return 0.7298, 1.49618, 1.49618, 0, 0
 
 
+# L-SHADE-Restart's convergence threshold on the population's error spread
+RESTART_TOL = 1e-8
+
+
+def _algo_settings(algo):
+    """(p, archive bound per individual) of an algorithm id (the product and
+    the oracle number algorithms alike): L-SHADE and L-SHADE-Restart take
+    L-SHADE's published p = 0.11 and archive 2.6 NP, JADE its p = 0.05 and
+    archive NP, the others p = 0.1."""
+    if algo in (_ALGO_LSHADE, _ALGO_LSHADE_RS):
+        return 0.11, 2.6
+    if algo == _ALGO_JADE:
+        return 0.05, 1.0
+    return 0.1, 2.6
+
+
 def _run_descs(S, specs):
-    """specs: list of (algo, func, dim, np, budget, instance, uid).  L-SHADE
-    takes its published settings: p = 0.11, archive 2.6 NP, final NP 4."""
+    """specs: list of (algo, func, dim, np, budget, instance, uid); final NP
+    4 for L-SHADE, JADE's c = 0.1."""
     out = []
     for sp in specs:
         (algo, func, dim, np_, budget, inst, uid) = sp
-        p = 0.11 if algo == S.ALGO_LSHADE else 0.1
+        p, r_arc = _algo_settings(algo)
         w, c1, c2, topo, vel = _pso_settings(sp)
-        out.append(S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, w,
-                             c1, c2, 0.2 * (W.UB - W.LB), p, 6, 2.6, 4, topo, vel))
+        d = S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, w,
+                      c1, c2, 0.2 * (W.UB - W.LB), p, 6, r_arc, 4, topo, vel)
+        d.c = 0.1
+        d.restart_tol = RESTART_TOL
+        out.append(d)
     return out
 
 
@@ -354,9 +378,10 @@ def _oracle_runs(specs, seconds):
     def one(sp):
         d = dict(zip(keys, sp))
         w, c1, c2, topo, vel = _pso_settings(sp)
+        p, r_arc = _algo_settings(d["algo"])
         d.update(lb=W.LB, ub=W.UB, F=0.5, CR=0.9, w=w, c1=c1, c2=c2,
-                 vmax=0.2 * (W.UB - W.LB), p=0.11 if d["algo"] == O.ALGO_LSHADE else 0.1, H=6,
-                 r_arc=2.6, np_min=4, topology=topo, velocity=vel)
+                 vmax=0.2 * (W.UB - W.LB), p=p, H=6, r_arc=r_arc, np_min=4, topology=topo,
+                 velocity=vel, c=0.1, restart_tol=RESTART_TOL)
         return O.run(d, W.BASE_SEED, W.INSTANCE_SEED)[0]["fes"]
 
     t0 = time.perf_counter()
@@ -436,6 +461,54 @@ def run_workload(a):
                            "10 instances, 2000 iterations, persistent fused kernels (one launch per "
                            "dimension class) replayed from a HIP graph",
                "evals": ev}, **extra)
+    elif a.workload in ("jade", "lshade_rs"):
+        algo = S.ALGO_JADE if a.workload == "jade" else S.ALGO_LSHADE_RS
+        spec = []
+        for r in range(2048):
+            f, d, k, np_ = W.c4_run(r)
+            spec.append((algo, f, d, np_, 10000 * d, k, r))
+        descs = _run_descs(S, spec)
+        n = len(descs)
+        res = torch.zeros((n, 32), dtype=torch.uint8, device="cuda")
+        st = torch.cuda.current_stream()
+        extra = {}
+        if algo == S.ALGO_JADE:
+            # with the parameter observer: (muF, muCR) after every generation
+            mu_len = max(d.budget // d.np for d in descs) + 2
+            mu = torch.empty(n * mu_len * 2, device="cuda")
+            call = lambda: ctx.run_observed(descs, res, mu, mu_len, stream=st)  # noqa: E731
+        else:
+            call = lambda: ctx.run(descs, res, stream=st)  # noqa: E731
+        call()   # warm-up (kernel set-up, instances)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        call()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        raw = res.cpu().numpy().tobytes()
+        rr = [S.RunResult.from_buffer_copy(raw[32 * k: 32 * (k + 1)]) for k in range(n)]
+        ev = sum(r.fes for r in rr)
+        extra["successes"] = sum(r.success for r in rr)
+        if algo == S.ALGO_JADE:
+            # the case study's curve: mean over runs of (muF, muCR) per generation
+            m = mu.view(n, mu_len, 2).cpu().numpy()
+            mean = np.nanmean(m, axis=0)
+            extra["mean_mu_by_generation"] = {str(g): [round(float(mean[g, 0]), 4), round(float(mean[g, 1]), 4)]
+                                              for g in (0, 1, 10, 100, 500) if g < mu_len}
+        else:
+            extra["restarts"] = sum(r.restarts for r in rr)
+        if not a.no_cpu:
+            extra["cpu_baseline"] = _oracle_runs([spec[(k * 129) % 2048] for k in range(16)], 10)
+        _line(metric, ev / (ms / 1e3), "evals/s", 1, 1, ms,
+              {"workload": ("batched JADE with the muF/muCR observer: 2048 runs, D in {10,30,50,100}, "
+                            "NP = min(18 D, 200), budget 10000 D, p = 0.05, c = 0.1, archive NP"
+                            if algo == S.ALGO_JADE else
+                            "batched L-SHADE-Restart: 2048 runs, D in {10,30,50,100}, NP from min(18 D, 200) "
+                            "down to 4 per restart, budget 10000 D, p = 0.11, H = 6, archive 2.6 NP, "
+                            f"restart once the population's error spread <= {RESTART_TOL:g}") +
+                           ", persistent fused kernels, one call", "evals": ev}, **extra)
     elif a.workload in ("c4", "lshade"):
         algo = S.ALGO_SHADE if a.workload == "c4" else S.ALGO_LSHADE
         spec = []
