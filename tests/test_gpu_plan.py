@@ -83,14 +83,20 @@ def test_plan_evaluate_matches_eager_and_replays_in_graph(ctx, precision):
 
 def run_descs():
     def desc(algo, func, dim, np_, budget, uid, inst=0):
-        return S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, 0.7298, 1.49618,
-                         1.49618, 0.2 * (UB - LB), 0.1, 6)
+        d = S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, 0.5, 0.9, 0.7298, 1.49618,
+                      1.49618, 0.2 * (UB - LB), 0.1, 6, 1.4, 4)
+        d.c = 0.1
+        d.restart_tol = 1e-2
+        return d
     return [desc(S.ALGO_DE, S.RASTRIGIN, 10, 50, 5000, 1),
             desc(S.ALGO_PSO, S.GRIEWANK, 30, 40, 4000, 2, inst=1),
             desc(S.ALGO_SHADE, S.SCHWEFEL, 50, 100, 5000, 3, inst=2),
             desc(S.ALGO_SHADE, S.ELLIPSOID, 100, 200, 4000, 4),
             desc(S.ALGO_PSO, S.ACKLEY, 10, 40, 3000, 5, inst=3),
-            desc(S.ALGO_PSO, S.ACKLEY, 10, 40, 3000, 6, inst=3)]
+            desc(S.ALGO_PSO, S.ACKLEY, 10, 40, 3000, 6, inst=3),
+            desc(S.ALGO_JADE, S.RASTRIGIN, 30, 60, 4000, 7, inst=1),
+            # restarts happen (Rosenbrock D = 10 converges to 1e-2 spread well within the budget)
+            desc(S.ALGO_LSHADE_RS, S.ROSENBROCK, 10, 50, 20000, 8, inst=2)]
 
 
 @pytest.mark.parametrize("team", ["", "wave"])
