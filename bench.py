@@ -79,13 +79,15 @@ def parse():
     ap.add_argument("--one-precision", action="store_true",
                     help="c2: time only --precision (default: also the other single precision, reported beside)")
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "lshade_rs", "jade", "psode", "cso", "copy"],
+                    choices=["c1", "c2", "c3", "c4", "c5", "lshade", "lshade_rs", "jade", "psode", "cso", "ops",
+                             "copy"],
                     help="c2 (default): batched evaluation sweep; c1: plain DE; c3: batched PSO; "
                          "c4: batched SHADE; c5: D=1000 evaluation; lshade: the c4 runs as L-SHADE; "
                          "lshade_rs: the c4 runs as L-SHADE-Restart; jade: the c4 runs as JADE with the "
                          "muF/muCR observer; "
                          "psode: the case study's PSO/DE hybrid, batched; "
                          "cso: the large-scale study's CSO runs at D=1000; "
+                         "ops: the unfused DE and PSO generation steps at scale; "
                          "copy: 512 MiB device copy "
                          "(calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -414,7 +416,65 @@ def run_workload(a):
     steps = max(1, min(a.steps, 5))
     warm = 1
     metric = "function evals/sec, batched FP32/split-BF16 vs plain FP64, at stated rel. error"
-    if a.workload == "c1":
+    if a.workload == "ops":
+        # the unfused generation steps at scale: 1024 populations of 2048 at
+        # D = 30 on one instance, x and u 252 MB each (beyond the 256 MB
+        # Infinity Cache together), one sevo_de_step / sevo_pso_step call per
+        # generation (variation or update, evaluation, selection or bests)
+        R, NP, D = 1024, 2048, 30
+        steps = max(1, min(a.steps, 20))
+        prob = S.problem(S.RASTRIGIN, D)
+        n = R * NP
+        st = torch.cuda.current_stream()
+        x = torch.empty(R * D * NP, device="cuda"); u = torch.empty_like(x)
+        ex = torch.empty(n, device="cuda"); eu = torch.empty_like(ex)
+        de = lambda t: S.DEState(R, NP, NP, D * NP, 7, t, x.data_ptr(), ex.data_ptr(),  # noqa: E731
+                                 u.data_ptr(), eu.data_ptr(), 0, 0)
+        ctx.de_step(prob, 0, de(0), 0.5, 0.9, stream=st)
+
+        def timed_calls(call, t0):
+            for k in range(warm):
+                call(t0 + k)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for k in range(steps):
+                call(t0 + warm + k)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ctx.sync(st)
+            return e0.elapsed_time(e1) / steps
+
+        ms_de = timed_calls(lambda t: ctx.de_step(prob, 0, de(t), 0.5, 0.9, stream=st), 1)
+        del u, eu
+        v = torch.empty_like(x); p = torch.empty_like(x)
+        ep = torch.empty(n, device="cuda"); gb = torch.zeros(R, dtype=torch.int32, device="cuda")
+        ps = lambda t: S.PSOState(R, NP, NP, D * NP, 9, t, x.data_ptr(), v.data_ptr(),  # noqa: E731
+                                  p.data_ptr(), ex.data_ptr(), ep.data_ptr(), gb.data_ptr())
+        vmax = 0.2 * (W.UB - W.LB)
+        ctx.pso_step(prob, 0, ps(0), 0.7298, 1.49618, 1.49618, vmax, stream=st)
+        ms_pso = timed_calls(lambda t: ctx.pso_step(prob, 0, ps(t), 0.7298, 1.49618, 1.49618, vmax,
+                                                    stream=st), 1)
+        # minimum HBM bytes per individual and generation: DE reads x, writes
+        # u, the evaluation reads u and writes e(u), the selection reads both
+        # errors (12 D + 12; the copy of winning trials is not counted); PSO
+        # reads x, v, p and writes x, v, the evaluation reads x and writes
+        # e(x), the bests read both errors (24 D + 12)
+        b_de, b_pso = n * (12 * D + 12), n * (24 * D + 12)
+        gbs_de = b_de / (ms_de / 1e3) / 1e9
+        gbs_pso = b_pso / (ms_pso / 1e3) / 1e9
+        _line(metric, n / (ms_de / 1e3), "evals/s", steps, warm, ms_de,
+              {"workload": "unfused DE rand/1/bin generation steps (sevo_de_step): 1024 populations x 2048 "
+                           "at D=30, Rastrigin, one instance, one call per generation; PSO iterations "
+                           "(sevo_pso_step) beside", "individuals": n},
+              roofline={"bound": "hbm", "achieved": round(gbs_de, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs_de / PEAK_HBM_GBS, 4), "traffic": None,
+                        "kernel": "the DE step's three launches (variation, evaluation, selection)",
+                        "algorithmic_bytes": b_de},
+              pso={"evals_per_s": round(n / (ms_pso / 1e3), 1), "ms": round(ms_pso, 4),
+                   "achieved_gbs": round(gbs_pso, 1), "frac": round(gbs_pso / PEAK_HBM_GBS, 4),
+                   "algorithmic_bytes": b_pso})
+    elif a.workload == "c1":
         spec = [(S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001, 0, 0)]
         descs = _run_descs(S, spec)
         ms64, r64 = _time_runs(ctx, S, torch, descs, S.FP64, steps, warm, trace_len=250)

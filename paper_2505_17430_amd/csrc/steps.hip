@@ -74,16 +74,37 @@ __global__ void k_de_variation(StepGeom g, T lb, T ub, T F, uint32_t thr, const 
     }
     const T *xr = x + (int64_t)r * g.rs;
     T *ur = u + (int64_t)r * g.rs;
-    for (int jb = 0; jb * 4 < g.dim; ++jb) {
-        const u32x4 w = draw(uid, g.seed32, g.t, (uint32_t)i, TAG_CROSS, (uint32_t)jb);
+    // chunks of VAR_CH coordinate blocks: all loads of a chunk (the parent
+    // and three donor gathers per coordinate, rows past dim clamped to the
+    // last) are issued before its stores, so a chunk costs one memory round
+    // trip instead of one per coordinate
+    constexpr int VAR_CH = 2;
+    const int nb = (g.dim + 3) / 4;
+    for (int jb0 = 0; jb0 < nb; jb0 += VAR_CH) {
+        T xi[VAR_CH][4], xa[VAR_CH][4], xb[VAR_CH][4], xc[VAR_CH][4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = jb * 4 + e;
-            if (j >= g.dim) break;
-            const int64_t row = (int64_t)j * g.ld;
-            const T v = xr[row + r1] + F * (xr[row + r2] - xr[row + r3]);
-            bool m;
-            ur[row + i] = cross_repair<T>(word(w, e), thr, j, jrand, v, xr[row + i], lb, ub, m);
+        for (int c = 0; c < VAR_CH; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = (int64_t)min((jb0 + c) * 4 + e, g.dim - 1) * g.ld;
+                xi[c][e] = xr[row + i];
+                xa[c][e] = xr[row + r1];
+                xb[c][e] = xr[row + r2];
+                xc[c][e] = xr[row + r3];
+            }
+#pragma unroll
+        for (int c = 0; c < VAR_CH; ++c) {
+            const int jb = jb0 + c;
+            if (jb >= nb) break;
+            const u32x4 w = draw(uid, g.seed32, g.t, (uint32_t)i, TAG_CROSS, (uint32_t)jb);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = jb * 4 + e;
+                if (j >= g.dim) break;
+                const T v = xa[c][e] + F * (xb[c][e] - xc[c][e]);
+                bool m;
+                ur[(int64_t)j * g.ld + i] = cross_repair<T>(word(w, e), thr, j, jrand, v, xi[c][e], lb, ub, m);
+            }
         }
     }
 }
@@ -101,9 +122,16 @@ __global__ void k_de_select(StepGeom g, T *__restrict__ x, T *__restrict__ ex, c
     if (replaced) replaced[e_at] = rep ? 1 : 0;
     if (!rep) return;
     ex[e_at] = eu[e_at];
-    for (int j = 0; j < g.dim; ++j) {
-        const int64_t at = (int64_t)r * g.rs + (int64_t)j * g.ld + i;
-        x[at] = u[at];
+    // chunks of 8 coordinates, loads before stores
+    constexpr int SEL_CH = 8;
+    const int64_t base = (int64_t)r * g.rs + i;
+    for (int j0 = 0; j0 < g.dim; j0 += SEL_CH) {
+        T v[SEL_CH];
+#pragma unroll
+        for (int c = 0; c < SEL_CH; ++c) v[c] = u[base + (int64_t)min(j0 + c, g.dim - 1) * g.ld];
+#pragma unroll
+        for (int c = 0; c < SEL_CH; ++c)
+            if (j0 + c < g.dim) x[base + (int64_t)(j0 + c) * g.ld] = v[c];
     }
 }
 
@@ -156,11 +184,19 @@ __global__ __launch_bounds__(256) void k_pso_best(StepGeom g, int init, const T 
         const int64_t e_at = (int64_t)r * g.ld + i;
         if (init || err_key(ex[e_at]) < err_key(ep[e_at])) {
             ep[e_at] = ex[e_at];
-            if (!init)
-                for (int j = 0; j < g.dim; ++j) {
-                    const int64_t at = (int64_t)r * g.rs + (int64_t)j * g.ld + i;
-                    p[at] = x[at];
+            if (!init) {
+                // chunks of 8 coordinates, loads before stores
+                constexpr int CP_CH = 8;
+                const int64_t base = (int64_t)r * g.rs + i;
+                for (int j0 = 0; j0 < g.dim; j0 += CP_CH) {
+                    T v[CP_CH];
+#pragma unroll
+                    for (int c = 0; c < CP_CH; ++c) v[c] = x[base + (int64_t)min(j0 + c, g.dim - 1) * g.ld];
+#pragma unroll
+                    for (int c = 0; c < CP_CH; ++c)
+                        if (j0 + c < g.dim) p[base + (int64_t)(j0 + c) * g.ld] = v[c];
                 }
+            }
         }
         const T k = err_key(ep[e_at]);
         if (k < bv || (k == bv && i < bi)) { bv = k; bi = i; }
