@@ -463,6 +463,17 @@ def run_workload(a):
         b_de, b_pso = n * (12 * D + 12), n * (24 * D + 12)
         gbs_de = b_de / (ms_de / 1e3) / 1e9
         gbs_pso = b_pso / (ms_pso / 1e3) / 1e9
+        del x, v, p, ex, ep
+        # the memory-bound side of the evaluation: D = 10 (2 D^2 = 200 FLOP
+        # per 44 B), 64 items of 262,144 points, 738 MB read per call
+        DE_, NE = 10, 1 << 18
+        xs = [torch.empty((DE_, NE), device="cuda").uniform_(W.LB, W.UB) for _ in range(64)]
+        es = [torch.empty(NE, device="cuda") for _ in range(64)]
+        batch = S.Context.prepare_batch([(S.problem(S.RASTRIGIN, DE_), k % 10, xs[k], es[k]) for k in range(64)])
+        ctx.tune_evaluate(batch, stream=st)
+        ms_ev = timed_calls(lambda t: ctx.evaluate_batch(batch, stream=st), 0)
+        b_ev = 64 * NE * (4 * DE_ + 4)
+        gbs_ev = b_ev / (ms_ev / 1e3) / 1e9
         _line(metric, n / (ms_de / 1e3), "evals/s", steps, warm, ms_de,
               {"workload": "unfused DE rand/1/bin generation steps (sevo_de_step): 1024 populations x 2048 "
                            "at D=30, Rastrigin, one instance, one call per generation; PSO iterations "
@@ -473,7 +484,11 @@ def run_workload(a):
                         "algorithmic_bytes": b_de},
               pso={"evals_per_s": round(n / (ms_pso / 1e3), 1), "ms": round(ms_pso, 4),
                    "achieved_gbs": round(gbs_pso, 1), "frac": round(gbs_pso / PEAK_HBM_GBS, 4),
-                   "algorithmic_bytes": b_pso})
+                   "algorithmic_bytes": b_pso},
+              evaluation_d10={"evals_per_s": round(64 * NE / (ms_ev / 1e3), 1), "ms": round(ms_ev, 4),
+                              "achieved_gbs": round(gbs_ev, 1), "frac": round(gbs_ev / PEAK_HBM_GBS, 4),
+                              "algorithmic_bytes": b_ev,
+                              "note": "64 items x 262144 points, Rastrigin D=10, batched evaluation"})
     elif a.workload == "c1":
         spec = [(S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001, 0, 0)]
         descs = _run_descs(S, spec)
