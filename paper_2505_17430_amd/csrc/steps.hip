@@ -125,9 +125,21 @@ __global__ __launch_bounds__(256) void k_de_variation_lds(StepGeom g, T lb, T ub
     const int r = blockIdx.x;
     const T *xr = x + (int64_t)r * g.rs;
     T *ur = u + (int64_t)r * g.rs;
-    for (int q = threadIdx.x; q < g.dim * g.np; q += 256) {
-        const int j = q / g.np, i = q - j * g.np;
-        sX[q] = xr[(int64_t)j * g.ld + i];
+    // staging in chunks of STAGE_CH elements per thread, all loads of a chunk
+    // (clamped, so always valid) issued before its stores
+    constexpr int STAGE_CH = 8;
+    const int n = g.dim * g.np;
+    for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
+        T v[STAGE_CH];
+#pragma unroll
+        for (int c = 0; c < STAGE_CH; ++c) {
+            const int q = min(q0 + c * 256, n - 1);
+            const int j = q / g.np, i = q - j * g.np;
+            v[c] = xr[(int64_t)j * g.ld + i];
+        }
+#pragma unroll
+        for (int c = 0; c < STAGE_CH; ++c)
+            if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
     }
     __syncthreads();
     const uint32_t uid = g.run_uid0 + (uint32_t)r;
