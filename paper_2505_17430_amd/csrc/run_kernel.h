@@ -382,12 +382,13 @@ __device__ __forceinline__ double check_f64(const Team<WAVE> &t, const RunDev &R
 // in the library workspace.
 // Algorithm families, one kernel each, so that a kernel holds only its own
 // algorithm's paths and registers.
-enum { FAM_DE = 0, FAM_SHADE = 1, FAM_LSHADE = 2, FAM_PSO = 3, FAM_PSODE = 4, NFAM = 5 };
+enum { FAM_DE = 0, FAM_SHADE = 1, FAM_LSHADE = 2, FAM_PSO = 3, FAM_PSODE = 4, FAM_LSHADE_RS = 5, NFAM = 6 };
 inline int family_of(int algo)
 {
     return algo == SEVO_ALGO_PSO ? FAM_PSO
          : algo == SEVO_ALGO_SHADE ? FAM_SHADE
-         : algo == SEVO_ALGO_LSHADE || algo == SEVO_ALGO_JADE || algo == SEVO_ALGO_LSHADE_RS ? FAM_LSHADE
+         : algo == SEVO_ALGO_LSHADE || algo == SEVO_ALGO_JADE ? FAM_LSHADE
+         : algo == SEVO_ALGO_LSHADE_RS ? FAM_LSHADE_RS
          : algo == SEVO_ALGO_PSODE ? FAM_PSODE
                                     : FAM_DE;
 }
@@ -445,7 +446,10 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     int np = R.np;   // L-SHADE shrinks it
     // the host launches each family's runs apart
     constexpr bool pso = FAM == FAM_PSO;
-    constexpr bool lshade = FAM == FAM_LSHADE;
+    // L-SHADE-Restart is L-SHADE with the restart block, kept in a kernel of
+    // its own so that the others do not carry its registers
+    constexpr bool rs_fam = FAM == FAM_LSHADE_RS;
+    constexpr bool lshade = FAM == FAM_LSHADE || rs_fam;
     // PSODE: a PSO move and a SHADE generation from the same population,
     // then the pairwise/3 selection
     constexpr bool psode = FAM == FAM_PSODE;
@@ -946,7 +950,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
         }
         fe += np;
         np = np_next;
-        if (lshade && R.restart && fe < R.budget) {
+        if (rs_fam && R.restart && fe < R.budget) {
             // L-SHADE-Restart: restart once the population's errors span at
             // most restart_tol (NaN counts as +infinity: never converged)
             float pv;
@@ -1041,6 +1045,7 @@ RunKernel run_table_shade(int ks, bool onchip, bool wave);
 RunKernel run_table_lshade(int ks, bool onchip, bool wave);
 RunKernel run_table_pso(int ks, bool onchip, bool wave);
 RunKernel run_table_psode(int ks, bool onchip, bool wave);
+RunKernel run_table_lshade_rs(int ks, bool onchip, bool wave);
 inline RunKernel run_table(int fam, int ks, bool onchip, bool wave)
 {
     switch (fam) {
@@ -1049,6 +1054,7 @@ inline RunKernel run_table(int fam, int ks, bool onchip, bool wave)
     case FAM_LSHADE: return run_table_lshade(ks, onchip, wave);
     case FAM_PSO: return run_table_pso(ks, onchip, wave);
     case FAM_PSODE: return run_table_psode(ks, onchip, wave);
+    case FAM_LSHADE_RS: return run_table_lshade_rs(ks, onchip, wave);
     default: return nullptr;
     }
 }
