@@ -206,22 +206,42 @@ __global__ void k_pso_update(StepGeom g, T lb, T ub, T w, T c1, T c2, T vmax, T 
     const uint32_t uid = g.run_uid0 + (uint32_t)r;
     const int gi = min(max((int)gbest[r], 0), g.np - 1);   // a stale index must not leave the run
     const int64_t base = (int64_t)r * g.rs;
-    for (int jb = 0; jb * 2 < g.dim; ++jb) {
-        const u32x4 wd = draw(uid, g.seed32, g.t, (uint32_t)i, TAG_PSO_R, (uint32_t)jb);
+    // chunks of UPD_CH coordinate pairs: all loads of a chunk (rows past dim
+    // clamped to the last) are issued before its stores
+    constexpr int UPD_CH = 4;
+    const int nb = (g.dim + 1) / 2;
+    for (int jb0 = 0; jb0 < nb; jb0 += UPD_CH) {
+        T xv[UPD_CH][2], vv[UPD_CH][2], pv[UPD_CH][2], gv[UPD_CH][2];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int j = jb * 2 + e;
-            if (j >= g.dim) break;
-            const int64_t row = base + (int64_t)j * g.ld;
-            const T r1 = (T)u24f(word(wd, 2 * e)), r2 = (T)u24f(word(wd, 2 * e + 1));
-            const T xj = x[row + i];
-            T vj = w * v[row + i] + c1 * r1 * (p[row + i] - xj) + c2 * r2 * (p[row + gi] - xj);
-            vj = vj > vmax ? vmax : (vj < -vmax ? -vmax : vj);
-            T xn = xj + vj;
-            if (xn < lb) { xn = lb; vj = T(0); }
-            else if (xn > ub) { xn = ub; vj = T(0); }
-            x[row + i] = xn;
-            v[row + i] = vj;
+        for (int c = 0; c < UPD_CH; ++c)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t row = base + (int64_t)min((jb0 + c) * 2 + e, g.dim - 1) * g.ld;
+                xv[c][e] = x[row + i];
+                vv[c][e] = v[row + i];
+                pv[c][e] = p[row + i];
+                gv[c][e] = p[row + gi];
+            }
+#pragma unroll
+        for (int c = 0; c < UPD_CH; ++c) {
+            const int jb = jb0 + c;
+            if (jb >= nb) break;
+            const u32x4 wd = draw(uid, g.seed32, g.t, (uint32_t)i, TAG_PSO_R, (uint32_t)jb);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int j = jb * 2 + e;
+                if (j >= g.dim) break;
+                const int64_t row = base + (int64_t)j * g.ld;
+                const T r1 = (T)u24f(word(wd, 2 * e)), r2 = (T)u24f(word(wd, 2 * e + 1));
+                const T xj = xv[c][e];
+                T vj = w * vv[c][e] + c1 * r1 * (pv[c][e] - xj) + c2 * r2 * (gv[c][e] - xj);
+                vj = vj > vmax ? vmax : (vj < -vmax ? -vmax : vj);
+                T xn = xj + vj;
+                if (xn < lb) { xn = lb; vj = T(0); }
+                else if (xn > ub) { xn = ub; vj = T(0); }
+                x[row + i] = xn;
+                v[row + i] = vj;
+            }
         }
     }
 }
