@@ -982,3 +982,108 @@ def test_lshade_restart_run_matches_replay(func, tol):
         assert k == gens - 1 or k == gens          # a restart after every generation with budget left
         assert all(s == np_ for s in sizes)          # the schedule never gets to shrink
     assert k > 0                                     # every case here restarts at least once
+
+
+# ------------------------------------------------------------------ PSO attraction terms
+# The update v = w v + c1 r1 (p - x) + c2 r2 (l - x) (the PSO module of Sec. 2.2,
+# Listing 1's inertia velocity with the global best or a ring neighbourhood
+# best l) is pinned from outside the oracle's code: by least squares on many
+# particles (the coefficients of p - x and l - x are c1 E[r1] = c1 / 2 and
+# c2 / 2, with c1 != c2 so that the two terms cannot be exchanged), and by
+# inverting single moves for r1 and r2, which must be the uniforms of the
+# documented Philox words (iteration t, particle i, tag PSO_R = 4, block
+# j div 2: words 0 and 1 for the even coordinate, 2 and 3 for the odd one).
+
+PSO_C1, PSO_C2 = 0.9, 2.1          # unequal, so that a p/l exchange shows
+FAR = 1e9                           # a box and a velocity bound that never bind
+
+
+def _u24_words(run_uid, t, i, block):
+    w = O.philox([t, i, (4 << 24) | block, 0], [run_uid, SEED & 0xFFFFFFFF ^ (SEED >> 32)])
+    return [int(x >> 8) * 2.0 ** -24 for x in w]
+
+
+def _pso_move(topology, X, V, P, eP, t, uid=4, w=0.0):
+    """One move of the oracle's inertia update (through the variant entry for
+    the ring, the classic entry for the global best) with nothing clamped."""
+    func = O.ELLIPSOID
+    D = X.shape[1]
+    o, M = O.instance(func, D, 0, ISEED)
+    if topology == 0:
+        st = dict(X=X, V=V, P=P, eX=np.zeros(X.shape[0]), eP=eP, g=int(np.argmin(eP)))
+        out = O.pso_iteration(func, -FAR, FAR, o, M, st, w, PSO_C1, PSO_C2, FAR, uid, SEED, t)
+        return out["X"], out["V"]
+    Xn, Vn, *_ = O.pso_variant_iteration(func, -FAR, FAR, o, M, X, V, P, np.zeros(X.shape[0]), eP, 1, 0, w,
+                                         PSO_C1, PSO_C2, FAR, uid, SEED, t)
+    return Xn, Vn
+
+
+@pytest.mark.parametrize("topology", [0, 1])
+def test_pso_attraction_terms_by_regression(topology):
+    """w = 0: the move is c1 r1 (p - x) + c2 r2 (l - x) per coordinate with
+    r1, r2 independent uniforms, so least squares on (p - x, l - x) gives
+    (c1 / 2, c2 / 2); swapping the two attractors or a sign fits far worse."""
+    rng = np.random.default_rng(11)
+    n, D = 2000, 12
+    X = rng.uniform(-50, 50, (n, D))
+    P = X + rng.normal(0, 30, (n, D))
+    eP = rng.uniform(1, 2, n)
+    V = rng.normal(0, 3, (n, D))          # w = 0: the old velocity must drop out
+    Xn, Vn = _pso_move(topology, X, V, P, eP, t=5)
+    if topology == 0:
+        L = np.tile(P[int(np.argmin(eP))], (n, 1))
+    else:
+        L = np.empty_like(P)
+        for i in range(n):
+            nb = [(i - 1) % n, i, (i + 1) % n]
+            L[i] = P[min(nb, key=lambda k: (eP[k], k))]
+    y = Vn.ravel()
+    assert np.allclose(Xn - X, Vn, rtol=1e-12, atol=1e-12)
+    A = np.stack([(P - X).ravel(), (L - X).ravel()], axis=1)
+    coef, res, *_ = np.linalg.lstsq(A, y, rcond=None)
+    assert np.all(np.abs(coef - [PSO_C1 / 2, PSO_C2 / 2]) < 0.03), coef
+    # residual variance of the two independent uniform terms: Var(r) = 1/12
+    pred_var = (PSO_C1 ** 2 * np.mean((P - X) ** 2) + PSO_C2 ** 2 * np.mean((L - X) ** 2)) / 12
+    assert res[0] / y.size == pytest.approx(pred_var, rel=0.1)
+
+
+@pytest.mark.parametrize("topology", [0, 1])
+def test_pso_attraction_draws_are_the_documented_words(topology):
+    """Particle 1 of a three-particle swarm whose best personal best is
+    particle 0's (its global best and its ring neighbourhood best).  With its
+    position on that best, only c1 r1 (p - x) is left: r1 = v / (c1 (p - x))
+    per coordinate.  With its position on its own personal best, only
+    c2 r2 (l - x) is left.  Both must be the u24 uniforms of the documented
+    Philox words, each coordinate its own pair (odd coordinates from words 2
+    and 3 of the block)."""
+    rng = np.random.default_rng(5)
+    D, t, uid = 9, 7, 13
+    P = rng.uniform(-60, 60, (3, D))
+    eP = np.array([1.0, 2.0, 3.0])
+    V = np.zeros((3, D))
+    want_r1 = np.array([_u24_words(uid, t, 1, j // 2)[2 * (j % 2)] for j in range(D)])
+    want_r2 = np.array([_u24_words(uid, t, 1, j // 2)[2 * (j % 2) + 1] for j in range(D)])
+    assert np.all(want_r1 != want_r2)
+    # state A: x_1 = l = P_0, so l - x vanishes
+    X = rng.uniform(-60, 60, (3, D)); X[1] = P[0]
+    _, Vn = _pso_move(topology, X, V, P, eP, t, uid)
+    r1 = Vn[1] / (PSO_C1 * (P[1] - X[1]))
+    assert np.allclose(r1, want_r1, rtol=1e-12, atol=0), (r1, want_r1)
+    # state B: x_1 = p_1, so p - x vanishes
+    X = rng.uniform(-60, 60, (3, D)); X[1] = P[1]
+    _, Vn = _pso_move(topology, X, V, P, eP, t, uid)
+    r2 = Vn[1] / (PSO_C2 * (P[0] - X[1]))
+    assert np.allclose(r2, want_r2, rtol=1e-12, atol=0), (r2, want_r2)
+
+
+def test_pso_inertia_term_is_w_v():
+    """With the particle on both attractors (x = p = l) only w v is left."""
+    D = 6
+    P = np.tile(np.linspace(-3, 3, D), (3, 1))
+    X = P.copy()
+    eP = np.array([1.0, 1.0, 1.0])
+    V = np.random.default_rng(2).normal(0, 2, (3, D))
+    for topology in (0, 1):
+        Xn, Vn = _pso_move(topology, X, V, P, eP, t=3, w=0.7298)
+        assert np.allclose(Vn, 0.7298 * V, rtol=1e-15, atol=0)
+        assert np.allclose(Xn - X, 0.7298 * V, rtol=1e-13, atol=1e-15)
