@@ -265,7 +265,9 @@ typedef struct {
     int32_t np_min;        /* L-SHADE: population size at the budget, 4 .. np */
     int32_t topology;      /* PSO, PSODE: 0 global best, 1 ring {i-1, i, i+1} (FP32 runs) */
     int32_t velocity;      /* PSO, PSODE: 0 inertia weight, 1 spherical (SPSO-2011; FP32 runs) */
-    int32_t reserved;      /* 0 */
+    int32_t max_generations; /* stop after this many generations (0: run to the budget); the budget
+                              still sets L-SHADE's size schedule, so a run stopped early is the same
+                              run up to that generation */
     double c;              /* JADE: adaptation rate of muF and muCR, 0 .. 1 (0.1 in JADE) */
     double restart_tol;    /* L-SHADE-Restart: restart once max e - min e over the population <= this */
 } sevo_run_desc;
@@ -356,6 +358,53 @@ int sevo_run(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t p
 int sevo_run_observed(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
                       sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
                       int32_t max_dim, float *mu, int64_t mu_len, void *stream);
+
+/* The state of each run when it stops (its budget or max_generations
+ * reached): the population, its errors and the adaptive state the next
+ * generation would start from.  Arrays are device memory owned by the
+ * caller, indexed by the run's position in `runs`; rows are max_np long
+ * and only a run's first np entries of a row are written (the rest keep
+ * their contents).  Populations are structure-of-arrays like every
+ * population of this library: coordinate d of individual i of run r is at
+ * [(r * max_dim + d) * max_np + i].
+ *   x, e     required: the population (PSO: the positions) and its errors.
+ *   u, eu    optional: the trials of the last generation and their errors
+ *            (DE, SHADE, L-SHADE, JADE, L-SHADE-Restart; PSODE: the DE
+ *            half's); not written for PSO or for a run that made no
+ *            generation.
+ *   v        optional: velocities (PSO, PSODE).
+ *   p, ep    optional: personal bests and their errors (PSO).
+ *   memory   optional [n_runs][32]: M_F[0..H-1] at 0..15 and M_CR[0..H-1]
+ *            at 16..31 (SHADE, L-SHADE, L-SHADE-Restart, PSODE; JADE: muF,
+ *            muCR in slot 0; a terminal CR slot holds -1).
+ *   archive  optional [n_runs][max_dim][max_arc]: the archive members
+ *            (L-SHADE, JADE, L-SHADE-Restart), member a of coordinate d at
+ *            [(r * max_dim + d) * max_arc + a].
+ *   counts   optional [n_runs][4]: the population size when the run stopped
+ *            (L-SHADE shrinks it), the archive size, the next memory slot
+ *            to be written, and the global best index (PSO and PSODE with
+ *            the global-best topology; 0 otherwise). */
+typedef struct {
+    int32_t max_np;        /* >= every run's np */
+    int32_t max_dim;       /* >= every run's dim */
+    int32_t max_arc;       /* >= round(r_arc np) of every archive run when `archive` is set */
+    int32_t reserved;      /* 0 */
+    float *x, *e;
+    float *u, *eu;
+    float *v;
+    float *p, *ep;
+    float *memory;
+    float *archive;
+    int32_t *counts;
+} sevo_run_state;
+
+/* sevo_run that also writes each run's final state to `state` (to continue
+ * or inspect runs, and to compare them generation by generation with another
+ * implementation).  Precision FP32, fused runs only (no CSO runs): otherwise
+ * SEVO_EUNSUPPORTED.  Everything else as sevo_run.  Asynchronous. */
+int sevo_run_snapshot(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+                      sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
+                      int32_t max_dim, const sevo_run_state *state, void *stream);
 
 /* ---- plans: work prepared once, then enqueued with launches only ----
  *

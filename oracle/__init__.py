@@ -465,6 +465,22 @@ class LShade:
         H = self.st.H
         return np.array(self.st.MF[:H]), np.array(self.st.MCR[:H]), self.st.pos
 
+    def archive(self):
+        return self.A[: self.st.na].copy()
+
+    def set_state(self, A, MF, MCR, pos):
+        """Take over an archive ([na, dim]) and a memory (H slots, next slot
+        pos) from elsewhere, e.g. another implementation's run state."""
+        A = np.asarray(A, dtype=np.float64)
+        if A.shape[0] > self.acap - 1:
+            raise ValueError("archive larger than its bound")
+        self.A[: A.shape[0]] = A
+        self.st.na = A.shape[0]
+        for k in range(self.st.H):
+            self.st.MF[k] = float(MF[k])
+            self.st.MCR[k] = float(MCR[k])
+        self.st.pos = int(pos)
+
     def generation(self, p, np_next, run_uid, seed, t):
         """Returns (trials U, their errors eU, number of successes)."""
         n = self.st.np

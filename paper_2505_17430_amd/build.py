@@ -7,6 +7,7 @@ paper_2505_17430_amd.build [--incremental]``.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -29,22 +30,34 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _headers_mtime():
-    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+def _inputs_digest(src: str) -> str:
+    """Digest of what an object is compiled from: the flags, the source and
+    every header.  It is read before the compiler starts, so an object whose
+    inputs change while it compiles is recompiled by the next build."""
+    hs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h"))
     hs.append(os.path.join(os.path.dirname(HERE), "include", "sevo.h"))
-    return max(os.path.getmtime(h) for h in hs)
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    for path in [src, *hs]:
+        with open(path, "rb") as f:
+            h.update(path.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def _compile(src: str, incremental: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    if incremental and os.path.exists(obj):
-        if os.path.getmtime(obj) >= max(os.path.getmtime(src), _headers_mtime()):
-            return obj
+    stamp = obj + ".inputs"
+    digest = _inputs_digest(src)
+    if incremental and os.path.exists(obj) and os.path.exists(stamp):
+        with open(stamp) as f:
+            if f.read().strip() == digest:
+                return obj
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-4000:]}")
     os.replace(obj + ".tmp", obj)
+    with open(stamp, "w") as f:
+        f.write(digest + "\n")
     return obj
 
 

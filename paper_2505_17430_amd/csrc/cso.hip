@@ -353,7 +353,8 @@ __global__ __launch_bounds__(CSO_THREADS) void k_cso_finish(const CsoDev *__rest
 int iterations_of(const sevo_run_desc &d)
 {
     const int64_t h = d.np / 2;
-    return d.budget <= d.np ? 0 : (int)((d.budget - d.np + h - 1) / h);
+    const int it = d.budget <= d.np ? 0 : (int)((d.budget - d.np + h - 1) / h);
+    return d.max_generations > 0 ? std::min(it, d.max_generations) : it;
 }
 
 }  // namespace

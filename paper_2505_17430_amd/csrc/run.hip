@@ -61,6 +61,7 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
             if (d.np < 2 || d.np > 1024 || d.np % 2 != 0)
                 return set_error(ctx, SEVO_EINVAL, "CSO needs an even swarm size in [2, 1024]");
             if (d.budget < 1) return set_error(ctx, SEVO_EINVAL, "budget < 1");
+            if (d.max_generations < 0) return set_error(ctx, SEVO_EINVAL, "max_generations < 0");
             if (!std::isfinite(d.c1)) return set_error(ctx, SEVO_EINVAL, "CSO needs a finite phi (c1)");
             if (precision == SEVO_FP64)
                 return set_error(ctx, SEVO_EUNSUPPORTED, "CSO runs take precision FP32 or SPLIT_BF16");
@@ -73,6 +74,7 @@ int validate_runs(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision
         const int min_np = d.algo == SEVO_ALGO_PSO ? 1 : 4;
         if (d.np < min_np || d.np > RUN_MAX_NP) return set_error(ctx, SEVO_EINVAL, "np outside [4 (1 for PSO), 256]");
         if (d.budget < 1) return set_error(ctx, SEVO_EINVAL, "budget < 1");
+        if (d.max_generations < 0) return set_error(ctx, SEVO_EINVAL, "max_generations < 0");
         if (d.algo == SEVO_ALGO_DE && (!std::isfinite(d.F) || !(d.CR >= 0 && d.CR <= 1)))
             return set_error(ctx, SEVO_EINVAL, "DE needs finite F and CR in [0, 1]");
         if (pso_like && !(d.vmax > 0))
@@ -133,7 +135,8 @@ static size_t onchip_limit(int ks, bool wave, int fam)
 }
 
 int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *results, float *trace,
-              int64_t trace_len, double *best_x, int max_dim, float *mu, int64_t mu_len, hipStream_t stream)
+              int64_t trace_len, double *best_x, int max_dim, float *mu, int64_t mu_len, const sevo_run_state *st,
+              hipStream_t stream)
 {
     // Team: runs of up to 64 individuals get one wave each (four runs of
     // one instance per workgroup), larger ones a whole workgroup.
@@ -238,6 +241,22 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         R.CR = (float)d.CR;
         R.restart = d.algo == SEVO_ALGO_LSHADE_RS ? 1 : 0;
         R.restart_tol = d.restart_tol;
+        R.gen_cap = d.max_generations;
+        if (st) {
+            R.st_np = st->max_np;
+            R.st_dim = st->max_dim;
+            R.st_arc = st->max_arc;
+            R.st_x = st->x;
+            R.st_e = st->e;
+            R.st_u = st->u;
+            R.st_eu = st->eu;
+            R.st_v = st->v;
+            R.st_p = st->p;
+            R.st_ep = st->ep;
+            R.st_mem = st->memory;
+            R.st_arc_out = st->archive;
+            R.st_cnt = st->counts;
+        }
         Group &G = groups[(ks_of(R.dim) * NFAM + family_of(d.algo)) * 4 + onchip[r] * 2 + wave[r]];
         G.runs.push_back(R);
         G.cost.push_back((double)d.budget * R.dim * R.dim);
@@ -306,13 +325,13 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
 // PSODE, the update-and-evaluate loop for CSO.
 int run_single(sevo_ctx *ctx, const sevo_run_desc *runs, int n, int precision, sevo_run_result *results,
                float *trace, int64_t trace_len, double *best_x, int max_dim, hipStream_t stream,
-               float *mu = nullptr, int64_t mu_len = 0)
+               float *mu = nullptr, int64_t mu_len = 0, const sevo_run_state *st = nullptr)
 {
     bool fused = false;
     for (int r = 0; r < n; ++r) fused |= runs[r].algo != SEVO_ALGO_CSO;
     int rc = SEVO_OK;
     if (fused &&
-        (rc = run_fused(ctx, runs, n, results, trace, trace_len, best_x, max_dim, mu, mu_len, stream)))
+        (rc = run_fused(ctx, runs, n, results, trace, trace_len, best_x, max_dim, mu, mu_len, st, stream)))
         return rc;
     return cso_runs(ctx, runs, n, precision, results, trace, trace_len, best_x, max_dim, stream);
 }
@@ -385,4 +404,27 @@ extern "C" int sevo_run_observed(sevo_ctx *ctx, const sevo_run_desc *runs, int32
         return run_single(ctx, runs, n_runs, precision, results, trace, trace_len, best_x, max_dim,
                           (hipStream_t)stream, mu, mu_len);
     return run_plain_f64(ctx, runs, n_runs, results, trace, trace_len, best_x, max_dim, (hipStream_t)stream);
+}
+
+extern "C" int sevo_run_snapshot(sevo_ctx *ctx, const sevo_run_desc *runs, int32_t n_runs, int32_t precision,
+                                 sevo_run_result *results, float *trace, int64_t trace_len, double *best_x,
+                                 int32_t max_dim, const sevo_run_state *state, void *stream)
+{
+    if (!ctx) return set_error(nullptr, SEVO_EINVAL, "ctx is NULL");
+    if (!results) return set_error(ctx, SEVO_EINVAL, "results is NULL");
+    if (!state || !state->x || !state->e) return set_error(ctx, SEVO_EINVAL, "state needs x and e");
+    int rc = validate_runs(ctx, runs, n_runs, precision, trace_len, trace, best_x, max_dim);
+    if (rc) return rc;
+    if (precision != SEVO_FP32) return set_error(ctx, SEVO_EUNSUPPORTED, "run states come from FP32 runs");
+    for (int r = 0; r < n_runs; ++r) {
+        const sevo_run_desc &d = runs[r];
+        if (d.algo == SEVO_ALGO_CSO) return set_error(ctx, SEVO_EUNSUPPORTED, "no run state for CSO runs");
+        if (d.np > state->max_np || d.prob.dim > state->max_dim)
+            return set_error(ctx, SEVO_EINVAL, "state rows shorter than a run's np or dim");
+        if (state->archive && archive_cap(d) > 0 && archive_cap(d) - 1 > state->max_arc)
+            return set_error(ctx, SEVO_EINVAL, "state archive narrower than a run's archive bound");
+    }
+    DeviceScope dg(ctx);
+    return run_single(ctx, runs, n_runs, precision, results, trace, trace_len, best_x, max_dim,
+                      (hipStream_t)stream, nullptr, 0, state);
 }

@@ -70,6 +70,13 @@ struct RunDev {
     // L-SHADE-Restart: restarts enabled, and the convergence threshold
     int32_t restart;
     double restart_tol;
+    // generations after which the run stops (0: at the budget)
+    int32_t gen_cap;
+    // the run's state when it stops (null: not wanted), rows of st_np
+    // points, st_dim rows per run, st_arc archive columns
+    int32_t st_np, st_dim, st_arc;
+    float *st_x, *st_e, *st_u, *st_eu, *st_v, *st_p, *st_ep, *st_mem, *st_arc_out;
+    int32_t *st_cnt;
 };
 
 // A team carries one run: the whole workgroup (256 threads, phases separated
@@ -605,9 +612,21 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     if (psode && R.topology == 0) global_best(sEX);
     fe = np;
 
-    while (fe < R.budget) {
+    // state rows of this run in the caller's snapshot arrays
+    const int64_t st_row = (int64_t)R.out_index * R.st_dim;
+    // a population [D][npp] and its errors into snapshot rows of st_np
+    auto put_state = [&](float *dst, float *dst_e, const float *Y, const float *eY) {
+        for (int j = wave; j < D; j += NW)
+            for (int i = lane; i < np; i += 64) dst[(st_row + j) * R.st_np + i] = Y[j * npp + i];
+        if (dst_e)
+            for (int i = tid; i < np; i += TS) dst_e[(int64_t)R.out_index * R.st_np + i] = eY[i];
+    };
+
+    while (fe < R.budget && (R.gen_cap <= 0 || gen < R.gen_cap)) {
         ++gen;
         const uint32_t tg = (uint32_t)gen;
+        // the generation after which the run stops (PSODE makes 2 np evaluations)
+        const bool last_gen = (R.gen_cap > 0 && gen >= R.gen_cap) || fe + (psode ? 2 : 1) * (int64_t)np >= R.budget;
         int np_next = np;   // L-SHADE: the size after this generation
         if constexpr (moves) {
             // ---- PSO: update, evaluate, personal and global bests ----
@@ -784,6 +803,7 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
             t.sync();
             eval_pop<KS, ONCHIP>(t, R, np, U, sEU, sA, sO, sT, K);
             t.sync();
+            if (last_gen && R.st_u) put_state(R.st_u, R.st_eu, U, sEU);
             record(U, sEU);
             // sums of dl, dl CR, dl CR^2, dl F^2, dl F, successes, successes with CR > 0
             double st[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -986,6 +1006,30 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
             row[0] = NAN;
             row[1] = NAN;
         }
+
+    // the state the run stopped in
+    if (R.st_x) {
+        put_state(R.st_x, R.st_e, X, sEX);
+        if (moves && R.st_v) put_state(R.st_v, nullptr, V, nullptr);
+        if (pso && R.st_p) put_state(R.st_p, R.st_ep, P, sEP);
+        if (shade && R.st_mem && tid < 16) {
+            R.st_mem[(int64_t)R.out_index * 32 + tid] = sMF[tid];
+            R.st_mem[(int64_t)R.out_index * 32 + 16 + tid] = sMCR[tid];
+        }
+        if (lshade && R.st_arc_out) {
+            const int na = sNaA[s];
+            for (int j = wave; j < D; j += NW)
+                for (int a = lane; a < na; a += 64)
+                    R.st_arc_out[(st_row + j) * R.st_arc + a] = R.Arc[(size_t)j * R.acap + a];
+        }
+        if (R.st_cnt && tid == 0) {
+            int32_t *c = R.st_cnt + (int64_t)R.out_index * 4;
+            c[0] = np;
+            c[1] = lshade ? sNaA[s] : 0;
+            c[2] = shade ? sPosA[s] : 0;
+            c[3] = moves && R.topology == 0 ? sGA[s] : 0;
+        }
+    }
 
     // results; the best point is re-evaluated in double once below 1e-6
     const float be = sBestBA[s];

@@ -548,7 +548,7 @@ int sevo::run_plain_f64(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_ru
             hipLaunchKernelGGL(k_record_f64, dim3(1), dim3(256), 0, s, X, eX, np, D, ld, fe, d.budget, rec, tr,
                                trace_len, bx);
             fe = np;
-            while (fe < d.budget) {
+            while (fe < d.budget && (d.max_generations <= 0 || gens < d.max_generations)) {
                 st.generation = (uint32_t)++gens;
                 if ((rc = sevo_de_step(ctx, &d.prob, d.instance, &st, &par, SEVO_FP64, s))) return rc;
                 // the trials are the generation's evaluations
@@ -564,7 +564,7 @@ int sevo::run_plain_f64(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_ru
                 hipLaunchKernelGGL(k_record_f64, dim3(1), dim3(256), 0, s, X, eX, np, D, ld, fe, d.budget, rec, tr,
                                    trace_len, bx);
                 fe += np;
-                if (fe >= d.budget) break;
+                if (fe >= d.budget || (d.max_generations > 0 && gens >= d.max_generations)) break;
                 st.iteration = (uint32_t)++gens;
             }
         }

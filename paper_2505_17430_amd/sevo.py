@@ -72,13 +72,21 @@ class RunDesc(C.Structure):
                 ("w", C.c_double), ("c1", C.c_double), ("c2", C.c_double), ("vmax", C.c_double),
                 ("p", C.c_double), ("H", C.c_int32),
                 ("r_arc", C.c_double), ("np_min", C.c_int32), ("topology", C.c_int32),
-                ("velocity", C.c_int32), ("reserved", C.c_int32), ("c", C.c_double),
+                ("velocity", C.c_int32), ("max_generations", C.c_int32), ("c", C.c_double),
                 ("restart_tol", C.c_double)]
 
 
 class RunResult(C.Structure):
     _fields_ = [("best_e", C.c_double), ("best_e32", C.c_float), ("success", C.c_int32),
                 ("fes", C.c_int64), ("generations", C.c_int32), ("restarts", C.c_int32)]
+
+
+class RunState(C.Structure):
+    _fields_ = [("max_np", C.c_int32), ("max_dim", C.c_int32), ("max_arc", C.c_int32),
+                ("reserved", C.c_int32),
+                ("x", C.c_void_p), ("e", C.c_void_p), ("u", C.c_void_p), ("eu", C.c_void_p),
+                ("v", C.c_void_p), ("p", C.c_void_p), ("ep", C.c_void_p), ("memory", C.c_void_p),
+                ("archive", C.c_void_p), ("counts", C.c_void_p)]
 
 
 def header_functions():
@@ -116,6 +124,8 @@ def lib():
                                 C.POINTER(PSOParams), i32, vp]
     L.sevo_run.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, vp]
     L.sevo_run_observed.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, vp, i64, vp]
+    L.sevo_run_snapshot.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32,
+                                    C.POINTER(RunState), vp]
     L.sevo_plan_evaluate.argtypes = [vp, C.POINTER(EvalItem), i32, i32, C.POINTER(vp)]
     L.sevo_plan_run.argtypes = [vp, C.POINTER(RunDesc), i32, i32, vp, vp, i64, vp, i32, C.POINTER(vp)]
     L.sevo_plan_launch.argtypes = [vp, vp]
@@ -302,3 +312,16 @@ class Context:
         self._check(self._L.sevo_run_observed(self._h, arr, len(descs), precision, _ptr(results),
                                               _ptr(trace), trace_len, _ptr(best_x), max_dim, _ptr(mu),
                                               mu_len, _stream(stream)))
+
+    def run_snapshot(self, descs, results, state, trace=None, trace_len=0, best_x=None, max_dim=0,
+                     precision=FP32, stream=None):
+        """sevo_run_snapshot: `state` a dict with max_np, max_dim, max_arc and
+        device buffers x, e (required), u, eu, v, p, ep, memory, archive,
+        counts (optional)."""
+        arr = (RunDesc * len(descs))(*descs)
+        st = RunState(state["max_np"], state["max_dim"], state.get("max_arc", 0), 0,
+                      *[_ptr(state.get(k)) for k in ("x", "e", "u", "eu", "v", "p", "ep", "memory",
+                                                     "archive", "counts")])
+        self._check(self._L.sevo_run_snapshot(self._h, arr, len(descs), precision, _ptr(results),
+                                              _ptr(trace), trace_len, _ptr(best_x), max_dim, C.byref(st),
+                                              _stream(stream)))

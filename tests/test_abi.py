@@ -43,6 +43,7 @@ STRUCTS = {
     "sevo_pso_params": (S.PSOParams, ["w", "c1", "c2", "vmax"]),
     "sevo_run_desc": (S.RunDesc, [f for f, _ in S.RunDesc._fields_]),
     "sevo_run_result": (S.RunResult, [f for f, _ in S.RunResult._fields_]),
+    "sevo_run_state": (S.RunState, [f for f, _ in S.RunState._fields_]),
 }
 
 
