@@ -93,7 +93,13 @@ def settings(fam):
 
 
 def run_desc(fam, func, dim, np_, budget, uid, cap, inst=0):
+    """A run stopped after `cap` generations; cap 0 is the initial
+    population alone (budget NP: max_generations 0 means no limit); cap
+    None runs to the budget."""
     algo, d = settings(fam)
+    if cap == 0:
+        budget = np_
+    cap = cap or 0
     return S.RunDesc(S.problem(func, dim), inst, uid, algo, np_, budget, d["F"], d["CR"], d["w"], d["c1"],
                      d["c2"], d["vmax"], d["p"], d["H"], d["r_arc"], d["np_min"], d["topology"], d["velocity"],
                      cap, d["c"], d["restart_tol"])
@@ -440,7 +446,7 @@ def test_ties_on_a_constant_function(ctx, team, monkeypatch):
                 # the reduction keeps the lowest indices, in order; no archive
                 assert cur["na"] == 0
                 assert np.array_equal(cur["X"], cur["U"][: cur["np"]]), fam
-            if fam.startswith("pso"):
+            if fam in ("pso", "pso_ring"):
                 assert np.array_equal(cur["P"], prev["P"]) and cur["g"] == 0, fam
     say(f"  {team}: ties resolved as the rules say for {TIE_FAMS}")
 
@@ -461,7 +467,7 @@ def test_free_runs_follow_oracle(ctx, fam):
         func = OTHER_FUNC[dim]
         np_ = {10: 30, 30: 50, 50: 64, 100: 120}[dim]
         mult = 2 if fam == "psode" or fam == "psode_gbest" else 1
-        descs.append(run_desc(fam, func, dim, np_, np_ * (1 + 3 * mult), 9700 + k, 0))
+        descs.append(run_desc(fam, func, dim, np_, np_ * (1 + 3 * mult), 9700 + k, None))
     tl = max(d.budget for d in descs) // 200
     snap = gpu_snapshot(ctx, descs, trace_len=tl)
     for r, d in enumerate(descs):
