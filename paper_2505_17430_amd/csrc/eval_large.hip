@@ -9,9 +9,15 @@
 // its own 32 rows of M (two 16-row MFMA tiles) from L2 and accumulates
 // 2 x 8 MFMA tiles.  Precision variants:
 //   FP32        v_mfma_f32_16x16x4_f32 on float operands;
-//   split bf16  every float is split into hi = bf16(f) and lo = bf16(f - hi);
-//               z += Mhi dhi + Mhi dlo + Mlo dhi on v_mfma_f32_16x16x32_bf16,
-//               accumulated in float (the lo*lo term is below float rounding).
+//   split bf16  every float is split into three bf16 terms, hi = bf16(f),
+//               mid = bf16(f - hi), lo = bf16(f - hi - mid), whose sum is f
+//               exactly; z += the six products of order 1 to 2^-16 (hi hi,
+//               hi mid, mid hi, hi lo, lo hi, mid mid) on
+//               v_mfma_f32_16x16x32_bf16, accumulated in float: the terms
+//               left out are below float rounding, so the result is as
+//               accurate as the FP32 path (two terms would leave each
+//               operand a 2^-17 representation error, which the objective
+//               can turn into more than 1e-5 e at a few hundred dimensions).
 // After the K loop each wave folds its rows into compensated per-point
 // partial sums; the workgroup writes one partial record per (row block,
 // point), and a second pass merges the row blocks in a fixed order and adds
@@ -119,15 +125,15 @@ __device__ __forceinline__ void merge_waves(float rec[4], const float (*sAcc)[PT
 // staging is a contiguous copy:
 //   FP32        [tile][chunk][32 k][128 points] floats; lanes store one
 //               coordinate row of 64 points, 256 contiguous bytes;
-//   split bf16  hi array then lo array, each [tile][chunk][128 points][32 k];
-//               the 8 coordinates of a lane are packed into one 16-byte
-//               vector per array and go through LDS so that the stores of a
-//               wave are 1 KB contiguous.
+//   split bf16  hi, mid and lo arrays one after another, each
+//               [tile][chunk][128 points][32 k]; the 8 coordinates of a lane
+//               are packed into one 16-byte vector per array and go through
+//               LDS so that the stores of a wave are 1 KB contiguous.
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_eval_operands(const EvalDesc *__restrict__ items, int n_items,
                                                        int total_blocks)
 {
-    __shared__ vu32x4 sH[BF16 ? 256 : 1], sL[BF16 ? 256 : 1];
+    __shared__ vu32x4 sT[BF16 ? 3 : 1][BF16 ? 256 : 1];
     const int L = xcd_remap_l(blockIdx.x, total_blocks);
     const EvalDesc &it = items[reinterpret_cast<const int32_t *>(items + n_items)[L]];
     const int dim = it.dim, n = it.n;
@@ -154,27 +160,31 @@ __global__ __launch_bounds__(256) void k_eval_operands(const EvalDesc *__restric
 #pragma unroll
         for (int e = 0; e < 8; ++e) D[(q * 8 + e) * 128] = v[e];
     } else {
-        uint16_t hi[8], lo[8];
+        // term t of each float (the remainder after the terms before it is
+        // exact in float, so hi + mid + lo = v)
+        uint16_t b[3][8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            hi[e] = to_bf16_rne(v[e]);
-            lo[e] = to_bf16_rne(v[e] - from_bf16(hi[e]));
+            float r = v[e];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                b[t][e] = to_bf16_rne(r);
+                r -= from_bf16(b[t][e]);
+            }
         }
-        vu32x4 vh, vl;
-        vh.x = hi[0] | ((uint32_t)hi[1] << 16); vh.y = hi[2] | ((uint32_t)hi[3] << 16);
-        vh.z = hi[4] | ((uint32_t)hi[5] << 16); vh.w = hi[6] | ((uint32_t)hi[7] << 16);
-        vl.x = lo[0] | ((uint32_t)lo[1] << 16); vl.y = lo[2] | ((uint32_t)lo[3] << 16);
-        vl.z = lo[4] | ((uint32_t)lo[5] << 16); vl.w = lo[6] | ((uint32_t)lo[7] << 16);
-        sH[lane * 4 + q] = vh;
-        sL[lane * 4 + q] = vl;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            vu32x4 vt;
+            vt.x = b[t][0] | ((uint32_t)b[t][1] << 16); vt.y = b[t][2] | ((uint32_t)b[t][3] << 16);
+            vt.z = b[t][4] | ((uint32_t)b[t][5] << 16); vt.w = b[t][6] | ((uint32_t)b[t][7] << 16);
+            sT[t][lane * 4 + q] = vt;
+        }
         __syncthreads();
         // chunk (tile pb / 2, kc) holds 512 vectors; this workgroup's 64
         // points are its half (pb & 1)
         const int64_t base = ((int64_t)(pb >> 1) * k32 + kc) * 512 + (pb & 1) * 256;
-        SEVO_GLOBAL vu32x4 *Bh = gout<vu32x4>(it.opnd);
-        SEVO_GLOBAL vu32x4 *Bl = gout<vu32x4>(it.opnd) + np * kp / 8;
-        Bh[base + threadIdx.x] = sH[threadIdx.x];
-        Bl[base + threadIdx.x] = sL[threadIdx.x];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) gout<vu32x4>(it.opnd)[t * (np * kp / 8) + base + threadIdx.x] = sT[t][threadIdx.x];
     }
 }
 
@@ -183,8 +193,7 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                                                     int total_blocks, Consts K)
 {
     __shared__ __attribute__((aligned(16))) float sB[BF16 ? 4 : KC * SB];
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[BF16 ? PT * SK : 8];
-    __shared__ __attribute__((aligned(16))) uint16_t sBl[BF16 ? PT * SK : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sBt[BF16 ? 3 : 1][BF16 ? PT * SK : 8];
     __shared__ float sZ0[4][PT];
     __shared__ float sZL[PT];
     __shared__ float sAcc[4][PT][4];
@@ -211,77 +220,95 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
 
     if constexpr (BF16) {
         // split operands from k_eval_operands: 128 points x 32 coordinates per
-        // chunk and array = 512 vectors of 8 bf16, two per thread; the next
-        // chunk's vectors and M fragments are loaded before this chunk's MFMAs
+        // chunk and term array = 512 vectors of 8 bf16, two per thread and
+        // term; the next chunk's vectors and M fragments are loaded before
+        // this chunk's MFMAs
         const int64_t kp = large_kpad(dim), np = large_npad(n);
         // global (not flat) loads: a flat load also counts against the LDS
         // counter, so the waits for this chunk's LDS reads would wait for the
         // next chunk's loads as well
-        const SEVO_GLOBAL vu32x4 *Bh = gin<vu32x4>(it.opnd);
-        const SEVO_GLOBAL vu32x4 *Bl = gin<vu32x4>(it.opnd) + np * kp / 8;
+        const SEVO_GLOBAL vu32x4 *Bt = gin<vu32x4>(it.opnd);
+        const int64_t tstride = np * kp / 8;   // vectors per term array
         // tiled layout: chunk kk of this point tile is 512 contiguous vectors
         const int v0 = threadIdx.x, v1 = threadIdx.x + 256;
         const int64_t g0 = (int64_t)pb * K32 * 512 + v0, g1 = g0 + 256;
         const int s0 = (v0 >> 2) * SK + (v0 & 3) * 8, s1 = (v1 >> 2) * SK + (v1 & 3) * 8;
         const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
-        const int64_t lo_off = (int64_t)RT * K32 * 512;
+        const int64_t mblock = (int64_t)RT * K32 * 512;   // bf16 per term block of M
         const int rt1 = act1 ? rt0 + 1 : rt0;
-        auto load_a = [&](int kk, bf16x8 &h0, bf16x8 &l0, bf16x8 &h1, bf16x8 &l1) {
+        // a[r][t]: term t of row tile r's fragment of chunk kk
+        auto load_a = [&](int kk, bf16x8 (&a)[2][3]) {
             const int64_t i0 = (((int64_t)min(rt0, RT - 1) * K32 + kk) * 64 + lane) * 8;
             const int64_t i1 = (((int64_t)min(rt1, RT - 1) * K32 + kk) * 64 + lane) * 8;
-            h0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i0);
-            l0 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i0);
-            h1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + i1);
-            l1 = *(const SEVO_GLOBAL bf16x8 *)(Mh + lo_off + i1);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                a[0][t] = *(const SEVO_GLOBAL bf16x8 *)(Mh + t * mblock + i0);
+                a[1][t] = *(const SEVO_GLOBAL bf16x8 *)(Mh + t * mblock + i1);
+            }
         };
         // M fragments of row tiles past the matrix are zeroed where they are
         // loaded, so that the MFMAs run unconditionally (a branch around them
         // makes the compiler copy the accumulators every iteration) and read
         // no register whose load may still be in flight at the loop head
         // (that would make it wait for the prefetch loads in the loop)
-        bf16x8 ah0, al0, ah1, al1;
-        load_a(0, ah0, al0, ah1, al1);
-        if (!act0) { ah0 = bf16x8{}; al0 = bf16x8{}; }
-        if (!act1) { ah1 = bf16x8{}; al1 = bf16x8{}; }
-        vu32x4 bh0 = Bh[g0], bh1 = Bh[g1], bl0 = Bl[g0], bl1 = Bl[g1];
-        *reinterpret_cast<vu32x4 *>(sBh + s0) = bh0;
-        *reinterpret_cast<vu32x4 *>(sBh + s1) = bh1;
-        *reinterpret_cast<vu32x4 *>(sBl + s0) = bl0;
-        *reinterpret_cast<vu32x4 *>(sBl + s1) = bl1;
+        bf16x8 a[2][3];
+        load_a(0, a);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (!act0) a[0][t] = bf16x8{};
+            if (!act1) a[1][t] = bf16x8{};
+        }
+        vu32x4 b0[3], b1[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            b0[t] = Bt[t * tstride + g0];
+            b1[t] = Bt[t * tstride + g1];
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            *reinterpret_cast<vu32x4 *>(sBt[t] + s0) = b0[t];
+            *reinterpret_cast<vu32x4 *>(sBt[t] + s1) = b1[t];
+        }
         __syncthreads();
         for (int kk = 0; kk < K32; ++kk) {
             const bool more = kk + 1 < K32;
-            bf16x8 nh0, nl0, nh1, nl1;
+            bf16x8 na[2][3];
             if (more) {
                 const int64_t d = (int64_t)(kk + 1) * 512;
-                bh0 = Bh[g0 + d];
-                bh1 = Bh[g1 + d];
-                bl0 = Bl[g0 + d];
-                bl1 = Bl[g1 + d];
-                load_a(kk + 1, nh0, nl0, nh1, nl1);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    b0[t] = Bt[t * tstride + g0 + d];
+                    b1[t] = Bt[t * tstride + g1 + d];
+                }
+                load_a(kk + 1, na);
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 const int off = (c * 16 + pc) * SK + kq * 8;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sBh + off);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBl + off);
-                z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, z[0][c], 0, 0, 0);
-                z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, z[0][c], 0, 0, 0);
-                z[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, z[0][c], 0, 0, 0);
-                z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z[1][c], 0, 0, 0);
-                z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z[1][c], 0, 0, 0);
-                z[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z[1][c], 0, 0, 0);
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sBt[0] + off);
+                const bf16x8 bm = *reinterpret_cast<const bf16x8 *>(sBt[1] + off);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBt[2] + off);
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    // smallest products first, so the float accumulation
+                    // loses the least of them
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][1], bm, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][2], bh, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][0], bl, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][1], bh, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][0], bm, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][0], bh, z[r][c], 0, 0, 0);
+                }
             }
             __syncthreads();
             if (more) {
-                *reinterpret_cast<vu32x4 *>(sBh + s0) = bh0;
-                *reinterpret_cast<vu32x4 *>(sBh + s1) = bh1;
-                *reinterpret_cast<vu32x4 *>(sBl + s0) = bl0;
-                *reinterpret_cast<vu32x4 *>(sBl + s1) = bl1;
-                ah0 = act0 ? nh0 : bf16x8{};
-                al0 = act0 ? nl0 : bf16x8{};
-                ah1 = act1 ? nh1 : bf16x8{};
-                al1 = act1 ? nl1 : bf16x8{};
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    *reinterpret_cast<vu32x4 *>(sBt[t] + s0) = b0[t];
+                    *reinterpret_cast<vu32x4 *>(sBt[t] + s1) = b1[t];
+                    a[0][t] = act0 ? na[0][t] : bf16x8{};
+                    a[1][t] = act1 ? na[1][t] : bf16x8{};
+                }
             }
             __syncthreads();
         }

@@ -41,10 +41,11 @@ struct EvalDesc {
     const float *Mfrag;     // [RT][KS][64] MFMA A-operand fragments of M (float)
     const float *tab;       // [RT * 16] per-row table (ellipsoid weight, 1/sqrt(i))
     const double *M64;      // [dim][dim] row-major
-    const uint16_t *Mbf;    // bf16 term blocks: D > 120 hi, lo [RT][KS32][64][8] in natural column
-                            // order; D <= 120 hi, mid, lo [RT][KS / 8][64][8] in the small path's order
+    const uint16_t *Mbf;    // bf16 term blocks hi, mid, lo: D > 120 [RT][KS32][64][8] in natural column
+                            // order; D <= 120 [RT][KS / 8][64][8] in the small path's order
     float *part;            // large-D partial sums [RB][n][8] (workspace)
-    void *opnd;             // large-D GEMM operands, 4 npad kpad bytes (workspace; layout at launch_eval_operands)
+    void *opnd;             // large-D GEMM operands, large_operand_size npad kpad bytes (workspace; layout
+                            // at k_eval_operands)
     int64_t ld;
     int32_t n;
     int32_t func;
@@ -99,6 +100,9 @@ hipError_t launch_eval_large_combine(const EvalDesc *d_items, int n_items, int t
 constexpr int OPERAND_POINTS = 64, OPERAND_K = 32;
 __host__ __device__ inline int64_t large_npad(int n) { return ((int64_t)n + LARGE_POINTS - 1) / LARGE_POINTS * LARGE_POINTS; }
 __host__ __device__ inline int64_t large_kpad(int dim) { return ((int64_t)dim + 31) / 32 * 32; }
+// bytes of GEMM operand per padded (point, coordinate): one float, or three
+// bf16 terms
+__host__ __device__ inline int64_t large_operand_size(bool split_bf16) { return split_bf16 ? 6 : 4; }
 hipError_t launch_eval_operands(const EvalDesc *d_items, int n_items, int total_blocks, bool split_bf16,
                                hipStream_t s);
 

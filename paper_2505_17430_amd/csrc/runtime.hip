@@ -137,8 +137,10 @@ struct DescSlot {
     char *h = nullptr, *d = nullptr;
     size_t cap = 0, used = 0;
     bool valid = false;          // device copy equals h[0, used)
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;   // recorded after the latest reader's kernels
+    hipStream_t stream = nullptr;   // the stream of the latest reader
 };
+
 
 struct sevo_ctx {
     int device = 0;
@@ -230,14 +232,14 @@ int upload_instance(sevo_ctx *ctx, DevInstance &I)
         if (I.func == ELLIPSOID) tab[r] = (float)std::pow(10.0, 6.0 * r / (double)(D - 1));
         else if (I.func == GRIEWANK) tab[r] = (float)(1.0 / (2.0 * M_PI * std::sqrt((double)(r + 1))));
     }
-    // bf16 terms of each float of M in the A-operand order of the 16x16x32
-    // bf16 MFMA (lane l holds row l % 16 and eight k-slots 8 (l / 16) + e),
-    // term blocks [RT][steps][64][8] one after another.
-    // D > 120 (the tiled GEMM): hi, lo; step kk, slot e is column
-    // 32 kk + 8 (l / 16) + e.
-    // D <= 120 (the small path): hi, mid, lo over the KS / 8 whole steps;
-    // step s, slot e is column 4 (8 s + e) + l / 16, the column the float
-    // path's k-step 8 s + e gives lane group l / 16.
+    // bf16 terms hi, mid, lo of each float of M (hi + mid + lo is the float
+    // exactly) in the A-operand order of the 16x16x32 bf16 MFMA (lane l
+    // holds row l % 16 and eight k-slots 8 (l / 16) + e), term blocks
+    // [RT][steps][64][8] one after another.
+    // D > 120 (the tiled GEMM): step kk, slot e is column 32 kk + 8 (l / 16) + e.
+    // D <= 120 (the small path): over the KS / 8 whole steps; step s, slot e
+    // is column 4 (8 s + e) + l / 16, the column the float path's k-step
+    // 8 s + e gives lane group l / 16.
     auto to_bf16 = [](float f) -> uint16_t {     // round to nearest even
         uint32_t u;
         std::memcpy(&u, &f, 4);
@@ -251,7 +253,7 @@ int upload_instance(sevo_ctx *ctx, DevInstance &I)
         return f;
     };
     const bool small = D <= SMALL_D_MAX;
-    const int terms = small ? 3 : 2;
+    const int terms = 3;
     const int steps = small ? KS / 8 : K32;
     const size_t block = (size_t)RT * steps * 64 * 8;
     std::vector<uint16_t> bf(std::max<size_t>(terms * block, 8), 0);
@@ -330,6 +332,10 @@ int stage_bytes(sevo_ctx *ctx, const std::vector<char> &blob, hipStream_t stream
     for (int k = 0; k < (int)ctx->slots.size(); ++k) {
         DescSlot &s = ctx->slots[k];
         if (s.used == n && s.valid && std::memcmp(s.h, blob.data(), n) == 0) {
+            // a reader on another stream first waits for the latest reader,
+            // which ran after the copy on its own stream; the event it then
+            // records (finish_slot) completes after every earlier reader
+            if (s.stream != stream) HIP_TRY(ctx, hipStreamWaitEvent(stream, s.done, 0));
             *d_out = s.d;
             *slot_out = k;
             return SEVO_OK;
@@ -362,6 +368,7 @@ int finish_slot_impl(sevo_ctx *ctx, int slot, hipStream_t stream)
 {
     if (slot < 0) return SEVO_OK;   // plan-owned table
     HIP_TRY(ctx, hipEventRecord(ctx->slots[slot].done, stream));
+    ctx->slots[slot].stream = stream;
     return SEVO_OK;
 }
 
@@ -414,7 +421,8 @@ size_t sevo::large_operand_bytes(const std::vector<EvalDesc> &items, int precisi
     size_t n = 0;
     if (precision == SEVO_FP64) return 0;
     for (const auto &d : items)
-        if (d.n > 0 && d.dim > SMALL_D_MAX) n += (size_t)(4 * large_npad(d.n) * large_kpad(d.dim));
+        if (d.n > 0 && d.dim > SMALL_D_MAX)
+            n += (size_t)(large_operand_size(precision == SEVO_SPLIT_BF16) * large_npad(d.n) * large_kpad(d.dim));
     return n;
 }
 
@@ -470,7 +478,7 @@ int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision
         for (auto &d : large) {
             const int64_t np = large_npad(d.n), kp = large_kpad(d.dim);
             d.opnd = static_cast<char *>(opnd) + ooff;
-            ooff += (size_t)(4 * np * kp);
+            ooff += (size_t)(large_operand_size(bf16) * np * kp);
             d.block0 = oblocks;
             d.nblocks = (int)((np / OPERAND_POINTS) * (kp / OPERAND_K));
             oblocks += d.nblocks;

@@ -2,13 +2,15 @@
 against the FP64 oracle, through the C ABI.
 
 Inputs come from ``workloads`` (seeded numpy) and the oracle's own instance
-generator; nothing the oracle sees comes from the GPU path.  Tolerance for the
-single-precision paths (FP32 MFMA rotation, split-bf16 rotation), relative to
-the error value e = f - f* (not to f, whose bias 100 would hide 1e-6):
-    |e_gpu - e_oracle| <= max(1e-6, 1e-5 e) + 4 eps32 ||x - o|| ||grad_z e||_1
-(tests/tolerance.py: the second term is the first-order propagation of the
-float32 rounding of z at ill-conditioned points).  Each check also prints how
-many points meet the bound without the conditioning term.
+generator; nothing the oracle sees comes from the GPU path.  The bound for
+the single-precision paths (FP32 MFMA rotation, split-bf16 rotation) is the
+one stated per function in tests/tolerance.py, relative to the error value
+e = f - f* (not to f, whose bias 100 would hide 1e-6):
+    |e_gpu - e_oracle| <= max(1e-6, 1e-5 e)
+for Ellipsoid, Rastrigin, Schwefel, Griewank and Ackley, plus for Rosenbrock
+the first-order effect of rounding the shifted point to float on the walls
+of its valley.  Each check prints the worst deviation as a fraction of the
+bound.
 """
 import sys
 
@@ -17,7 +19,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.tolerance import strict_tolerance, tolerance
+from tests.tolerance import tolerance
 
 torch = pytest.importorskip("torch")
 from paper_2505_17430_amd import sevo as S  # noqa: E402
@@ -54,19 +56,17 @@ def gpu_eval(ctx, func, dim, inst, X, precision=S.FP32, pad=5):
     return out[:n].astype(np.float64)
 
 
-def check(e_gpu, e_ora, what, rel=1e-5, abs_=1e-6, tol=None):
-    strict = strict_tolerance(e_ora, rel, abs_)
-    tol = strict if tol is None else tol
+def check(e_gpu, e_ora, what, tol):
     dev = np.abs(e_gpu - e_ora)
     bad = np.nonzero(~(dev <= tol))[0]
     worst = float(np.max(dev / tol)) if len(dev) else 0.0
-    n_strict = int(np.sum(dev <= strict))
-    say(f"  {what}: n={len(e_ora)} worst dev/tol={worst:.3g} strict-bound ok {n_strict}/{len(e_ora)}")
+    say(f"  {what}: n={len(e_ora)} worst |de| / bound = {worst:.3g}")
     assert len(bad) == 0, (what, bad[:5], e_gpu[bad[:5]], e_ora[bad[:5]])
 
 
 def check_f32(e_gpu, func, o, M, X, e_ora, what):
-    check(e_gpu, e_ora, what, tol=tolerance(func, o, M, X, e_ora))
+    """Single precision against the bound stated for the function."""
+    check(e_gpu, e_ora, what, tolerance(func, o, M, X, e_ora))
 
 
 SMALL_DIMS = [2, 3, 7, 10, 16, 30, 50, 64, 100, 120]
@@ -129,8 +129,9 @@ def test_parity_split_bf16(ctx, dim):
 def test_parity_fp64(ctx, dim):
     for func in range(6):
         o, M, X = _points(func, dim, 2, n=100)
-        check(gpu_eval(ctx, func, dim, 2, X.astype(np.float64), precision=S.FP64),
-              O.errors_soa_f32(func, o, M, X), f"fp64 f{func} D{dim}", rel=1e-11, abs_=1e-12)
+        eo = O.errors_soa_f32(func, o, M, X)
+        check(gpu_eval(ctx, func, dim, 2, X.astype(np.float64), precision=S.FP64), eo, f"fp64 f{func} D{dim}",
+              np.maximum(1e-12, 1e-11 * np.abs(eo)))
 
 
 @pytest.mark.parametrize("dim", [2, 10, 30, 100, 120, 200, 1000])
