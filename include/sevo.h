@@ -169,6 +169,25 @@ typedef struct {
 int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
                         int32_t precision, void *stream);
 
+/* sevo_evaluate_batch for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc): the
+ * call allocates nothing.  Its descriptor tables go to a fixed device array
+ * of the library, 1 MiB per GPU (about 16,000 items of 64 B plus 4 B per
+ * tile of 64 to 128 points), held by every GPU the library runs on until the
+ * process ends and shared by every call on that GPU: calls that overlap on
+ * one GPU (other streams, other contexts) race on it; calls on one stream
+ * are ordered.  Results are those of sevo_evaluate_batch, bit for bit.
+ * Limits, each a clear error and nothing enqueued:
+ *   - every item's instance must already be resident on the context (made by
+ *     sevo_instance, sevo_set_instance or an earlier evaluation or run):
+ *     otherwise SEVO_ESTATE;
+ *   - precision FP32 or SPLIT_BF16 takes D <= 120 only (larger D needs the
+ *     GEMM workspace): otherwise SEVO_EUNSUPPORTED; FP64 takes any D;
+ *   - tables beyond the array's 1 MiB: SEVO_EINVAL.
+ * The host tables are copied with hipMemcpyAsync on `stream`.  Asynchronous. */
+int sevo_evaluate_batch_noalloc(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
+                                int32_t precision, void *stream);
+
 /* Autotuning of the batched evaluation (optional).  For every dimension
  * class (k-steps ceil(D/4), D <= 120) present in `items`, times the launch
  * shapes that cannot change any result -- the resident persistent grid and

@@ -141,6 +141,12 @@ struct DescSlot {
     hipStream_t stream = nullptr;   // the stream of the latest reader
 };
 
+// The device array behind sevo_evaluate_batch_noalloc: the descriptor tables
+// of one call, packed at 256-byte offsets.  Every GPU holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress gives for the context's device (sevo_ctx::scratch).
+constexpr size_t NOALLOC_TABLE_BYTES = (size_t)1 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_TABLE_BYTES];
 
 struct sevo_ctx {
     int device = 0;
@@ -158,6 +164,7 @@ struct sevo_ctx {
     sevo_plan *rec = nullptr;           // plan being built (calls record instead of launching)
     std::vector<hipStream_t> streams;   // internal, default priority
     std::vector<hipEvent_t> fork_ev;    // one per internal stream + the fork event
+    char *scratch = nullptr;            // device address of `scratch` on this context's GPU
 };
 
 // A prepared call: plan-owned device memory and the launches to enqueue.
@@ -747,6 +754,9 @@ int sevo_create(sevo_ctx **out, int32_t hip_device, uint64_t base_seed, uint64_t
     ctx->consts = make_consts();
     if (const char *e = std::getenv("SEVO_TILES_PER_BLOCK")) ctx->tiles_per_block = std::atoi(e);
     DeviceGuard g(hip_device);
+    e = hipGetSymbolAddress((void **)&ctx->scratch, HIP_SYMBOL(scratch));
+    if (e != hipSuccess)
+        return fail(nullptr, SEVO_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
     ctx->slots.resize(16);
     for (auto &s : ctx->slots) {
         e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
@@ -901,6 +911,70 @@ int sevo_evaluate_batch(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_it
     std::vector<std::pair<EvalDesc, int>> v;
     if ((rc = build_items(ctx, items, n_items, v))) return rc;
     return eval_items(ctx, v, precision, (hipStream_t)stream);
+}
+
+int sevo_evaluate_batch_noalloc(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items,
+                                int32_t precision, void *stream)
+{
+    if (!ctx) return fail(nullptr, SEVO_EINVAL, "ctx is NULL");
+    int rc = check_precision(ctx, precision);
+    if (rc) return rc;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, SEVO_EINVAL, "bad item list");
+    DeviceGuard g(ctx->device);
+    std::vector<EvalDesc> v;
+    v.reserve(n_items);
+    for (int i = 0; i < n_items; ++i) {
+        const sevo_eval_item &it = items[i];
+        if ((rc = check_problem(ctx, &it.prob))) return rc;
+        if (it.n < 0) return fail(ctx, SEVO_EINVAL, "item %d: n = %d", i, it.n);
+        if (it.n == 0) continue;
+        if (it.ld < it.n) return fail(ctx, SEVO_EINVAL, "item %d: ld %lld < n %d", i, (long long)it.ld, it.n);
+        if (it.ld > MAX_LD) return fail(ctx, SEVO_EINVAL, "item %d: ld %lld > 2^28", i, (long long)it.ld);
+        if (!it.x || !it.err_out) return fail(ctx, SEVO_EINVAL, "item %d: null buffer", i);
+        if (precision != SEVO_FP64 && it.prob.dim > SMALL_D_MAX)
+            return fail(ctx, SEVO_EUNSUPPORTED,
+                        "item %d: D = %d > %d needs the GEMM workspace (sevo_evaluate_batch)", i, it.prob.dim,
+                        SMALL_D_MAX);
+        // no instance is made here: that would allocate
+        auto itr = ctx->cache.find(std::make_tuple((int)it.prob.func, (int)it.prob.dim, it.instance));
+        if (itr == ctx->cache.end())
+            return fail(ctx, SEVO_ESTATE,
+                        "item %d: instance %u of (func %d, D %d) is not resident; make it first "
+                        "(sevo_instance or any other evaluation)", i, it.instance, it.prob.func, it.prob.dim);
+        const DevInstance &I = *itr->second;
+        EvalDesc d{};
+        d.x = it.x;
+        d.err = it.err_out;
+        d.o = I.d_o;
+        d.Mfrag = I.d_Mfrag;
+        d.tab = I.d_tab;
+        d.M64 = I.d_M64;
+        d.Mbf = I.d_Mbf;
+        d.ld = it.ld;
+        d.n = it.n;
+        d.func = it.prob.func;
+        d.dim = it.prob.dim;
+        v.push_back(d);
+    }
+    std::vector<PreparedLaunch> pl;
+    if ((rc = prepare_eval(ctx, std::move(v), precision, nullptr, nullptr, pl))) return rc;
+    size_t need = 0;
+    for (const auto &p : pl) need += (p.table.size() + 255) & ~(size_t)255;
+    if (need > NOALLOC_TABLE_BYTES)
+        return fail(ctx, SEVO_EINVAL, "the call's descriptor tables take %zu bytes; the static table holds %zu",
+                    need, NOALLOC_TABLE_BYTES);
+    // tables into the device array, each launch after its table on the
+    // caller's stream (so a later call on the same stream rewrites them only
+    // after these kernels)
+    size_t off = 0;
+    for (auto &p : pl) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->scratch + off, p.table.data(), p.table.size(), hipMemcpyHostToDevice,
+                                    (hipStream_t)stream));
+        p.L.d = ctx->scratch + off;
+        if ((rc = emit_launch(ctx, p.L, (hipStream_t)stream))) return rc;
+        off += (p.table.size() + 255) & ~(size_t)255;
+    }
+    return SEVO_OK;
 }
 
 int sevo_tune_evaluate(sevo_ctx *ctx, const sevo_eval_item *items, int32_t n_items, int32_t precision,

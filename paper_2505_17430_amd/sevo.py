@@ -117,6 +117,7 @@ def lib():
     L.sevo_generate_instance.argtypes = [i32, i32, u32, u64, vp, vp]
     L.sevo_evaluate.argtypes = [vp, C.POINTER(Problem), u32, vp, i64, i32, vp, i32, vp]
     L.sevo_evaluate_batch.argtypes = [vp, C.POINTER(EvalItem), i32, i32, vp]
+    L.sevo_evaluate_batch_noalloc.argtypes = [vp, C.POINTER(EvalItem), i32, i32, vp]
     L.sevo_tune_evaluate.argtypes = [vp, C.POINTER(EvalItem), i32, i32, vp, C.POINTER(i32)]
     L.sevo_de_step.argtypes = [vp, C.POINTER(Problem), u32, C.POINTER(DEState),
                                C.POINTER(DEParams), i32, vp]
@@ -267,6 +268,12 @@ class Context:
         """items: list of (prob, inst, x, err[, n, ld]) or a prepare_batch() result."""
         arr = items if isinstance(items, C.Array) else self.prepare_batch(items)
         self._check(self._L.sevo_evaluate_batch(self._h, arr, len(arr), precision, _stream(stream)))
+
+    def evaluate_batch_noalloc(self, items, precision=FP32, stream=None):
+        """sevo_evaluate_batch_noalloc: the same evaluation with no device
+        allocation (instances must be resident; D <= 120 in single precision)."""
+        arr = items if isinstance(items, C.Array) else self.prepare_batch(items)
+        self._check(self._L.sevo_evaluate_batch_noalloc(self._h, arr, len(arr), precision, _stream(stream)))
 
     def tune_evaluate(self, items, precision=FP32, stream=None):
         """Autotune the evaluation launch shape on these items; returns
