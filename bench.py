@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="c2: leave out the FP64 comparison legs and C1 (vs_baseline is then null); for "
+                         "profiler runs, where their 12,000 small launches are slow")
     ap.add_argument("--one-precision", action="store_true",
                     help="c2: time only --precision (default: also the other single precision, reported beside)")
     ap.add_argument("--workload", default="c2",
@@ -279,46 +282,48 @@ def main():
                 "ms_per_step": round(ms_, 4), "evals_per_s": round(n_evals / (ms_ / 1e3), 1),
                 "d100_kernel_ms": round(d_, 4),
                 "d100_tflops_fp32_equiv": round(flops100 / (d_ / 1e3) / 1e12, 3)}
-    # the plain FP64 path over the same sweep: the same batched calls and
-    # timing with double inputs, shift, rotation and sum (k_eval_f64), one
-    # replica (its working set alone exceeds the Infinity Cache)
-    reps64 = replicas(torch.float64, 1)
-    f64_steps = max(1, min(a.steps, 10))
-    ms64, d100_64, _ = timed(S.FP64, reps64, f64_steps, 1, tune=False)
-    # the same in one launch per run: each run's 100-point population of each
-    # (function, D, instance) evaluated by its own sevo_evaluate call
-    singles = [(S.problem(f, d), k, x[:, r * W.C2_POINTS_PER_RUN:(r + 1) * W.C2_POINTS_PER_RUN],
-                e[r * W.C2_POINTS_PER_RUN:(r + 1) * W.C2_POINTS_PER_RUN])
-               for (f, d, k, x, e) in keep0(reps64) for r in range(W.C2_RUNS)]
-    for (pb, k, x, e) in singles[:64]:
-        ctx.evaluate(pb, k, x, e, n=x.shape[1], ld=x.stride(0), precision=S.FP64, stream=stream)
-    torch.cuda.synchronize()
-    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    p0.record(stream)
-    for (pb, k, x, e) in singles:
-        ctx.evaluate(pb, k, x, e, n=x.shape[1], ld=x.stride(0), precision=S.FP64, stream=stream)
-    p1.record(stream)
-    torch.cuda.synchronize()
-    ms_per_run = p0.elapsed_time(p1)
-    del reps64, singles
-    fp64 = {"batched": {"ms_per_step": round(ms64, 4), "evals_per_s": round(n_evals / (ms64 / 1e3), 1),
-                        "d100_kernel_ms": round(d100_64, 4), "steps": f64_steps,
-                        "path": "sevo_evaluate_batch, precision FP64 (k_eval_f64), the same calls and "
-                                "event timing as the single-precision legs"},
-            "one_run_per_launch": {"ms_per_step": round(ms_per_run, 3),
-                                   "evals_per_s": round(n_evals / (ms_per_run / 1e3), 1),
-                                   "launches_per_step": len(groups) * W.C2_RUNS,
-                                   "path": "one sevo_evaluate call (FP64) per run's 100-point population"}}
-    speedup = ms64 / ms_step
-    # C1, the plain DE configuration: the fused FP32 run (graph replay of a
-    # plan) against the plain FP64 path's one launch per step
-    c1_descs = _run_descs(S, [(S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001, 0, 0)])
-    c1_64, c1r64 = _time_runs(ctx, S, torch, c1_descs, S.FP64, 3, 1, trace_len=250)
-    c1_32, c1r32 = _time_runs(ctx, S, torch, c1_descs, S.FP32, 3, 1, trace_len=250, graph=True)
-    c1 = {"workload": "plain DE rand/1/bin, one run: Rastrigin D=10, NP=50, F=0.5, CR=0.9, 1000 generations",
-          "plain_fp64_ms": round(c1_64, 3), "fused_fp32_ms": round(c1_32, 3),
-          "speedup_fused_vs_plain": round(c1_64 / c1_32, 2),
-          "evals": int(c1r64[0].fes), "best_e_fp64": c1r64[0].best_e, "best_e_fp32": c1r32[0].best_e}
+    fp64, c1, speedup = None, None, None
+    if not a.no_fp64:
+        # the plain FP64 path over the same sweep: the same batched calls and
+        # timing with double inputs, shift, rotation and sum (k_eval_f64), one
+        # replica (its working set alone exceeds the Infinity Cache)
+        reps64 = replicas(torch.float64, 1)
+        f64_steps = max(1, min(a.steps, 10))
+        ms64, d100_64, _ = timed(S.FP64, reps64, f64_steps, 1, tune=False)
+        # the same in one launch per run: each run's 100-point population of each
+        # (function, D, instance) evaluated by its own sevo_evaluate call
+        singles = [(S.problem(f, d), k, x[:, r * W.C2_POINTS_PER_RUN:(r + 1) * W.C2_POINTS_PER_RUN],
+                    e[r * W.C2_POINTS_PER_RUN:(r + 1) * W.C2_POINTS_PER_RUN])
+                   for (f, d, k, x, e) in keep0(reps64) for r in range(W.C2_RUNS)]
+        for (pb, k, x, e) in singles[:64]:
+            ctx.evaluate(pb, k, x, e, n=x.shape[1], ld=x.stride(0), precision=S.FP64, stream=stream)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for (pb, k, x, e) in singles:
+            ctx.evaluate(pb, k, x, e, n=x.shape[1], ld=x.stride(0), precision=S.FP64, stream=stream)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        ms_per_run = p0.elapsed_time(p1)
+        del reps64, singles
+        fp64 = {"batched": {"ms_per_step": round(ms64, 4), "evals_per_s": round(n_evals / (ms64 / 1e3), 1),
+                            "d100_kernel_ms": round(d100_64, 4), "steps": f64_steps,
+                            "path": "sevo_evaluate_batch, precision FP64 (k_eval_f64), the same calls and "
+                                    "event timing as the single-precision legs"},
+                "one_run_per_launch": {"ms_per_step": round(ms_per_run, 3),
+                                       "evals_per_s": round(n_evals / (ms_per_run / 1e3), 1),
+                                       "launches_per_step": len(groups) * W.C2_RUNS,
+                                       "path": "one sevo_evaluate call (FP64) per run's 100-point population"}}
+        speedup = ms64 / ms_step
+        # C1, the plain DE configuration: the fused FP32 run (graph replay of a
+        # plan) against the plain FP64 path's one launch per step
+        c1_descs = _run_descs(S, [(S.ALGO_DE, S.RASTRIGIN, 10, 50, 50 * 1001, 0, 0)])
+        c1_64, c1r64 = _time_runs(ctx, S, torch, c1_descs, S.FP64, 3, 1, trace_len=250)
+        c1_32, c1r32 = _time_runs(ctx, S, torch, c1_descs, S.FP32, 3, 1, trace_len=250, graph=True)
+        c1 = {"workload": "plain DE rand/1/bin, one run: Rastrigin D=10, NP=50, F=0.5, CR=0.9, 1000 generations",
+              "plain_fp64_ms": round(c1_64, 3), "fused_fp32_ms": round(c1_32, 3),
+              "speedup_fused_vs_plain": round(c1_64 / c1_32, 2),
+              "evals": int(c1r64[0].fes), "best_e_fp64": c1r64[0].best_e, "best_e_fp32": c1r32[0].best_e}
 
     achieved = flops100 / (d100_ms / 1e3) / 1e12
     if prec == S.FP32:
@@ -347,7 +352,7 @@ def main():
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(speedup, 3),
+        "vs_baseline": None if speedup is None else round(speedup, 3),
         "vs_baseline_is": "speed-up over the plain FP64 path on the same sweep (fp64.batched), "
                           "at the asserted bound max(1e-6, 1e-5 e)",
         "dtype": "f32" if prec == S.FP32 else "bf16x6",
@@ -365,9 +370,10 @@ def main():
                                 "schwefel, griewank, ackley; rosenbrock + 4 eps32 |x - o|_2 |grad_z e|_1 "
                                 "(asserted by the parity tests; measured below under accuracy)"},
         "roofline": roof,
-        "fp64": fp64,
-        "c1": c1,
     }
+    if fp64 is not None:
+        out["fp64"] = fp64
+        out["c1"] = c1
     if legs:
         out["precisions"] = legs
     if not a.no_cpu:
@@ -563,6 +569,18 @@ def run_workload(a):
         ctx.de_step(prob, 0, de2(0), 0.5, 0.9, stream=st)
         ms_de2 = timed_calls(lambda t: ctx.de_step(prob, 0, de2(t), 0.5, 0.9, stream=st), 1)
         del x2, u2, ex2, eu2
+        # C4's largest populations: 4096 runs of 200 at D = 100 (80 KB each,
+        # staged through LDS in slabs of rows), 328 MB per population buffer
+        R3, NP3, D3 = 4096, 200, 100
+        n3 = R3 * NP3
+        prob3 = S.problem(S.RASTRIGIN, D3)
+        x3 = torch.empty(R3 * D3 * NP3, device="cuda"); u3 = torch.empty_like(x3)
+        ex3 = torch.empty(n3, device="cuda"); eu3 = torch.empty_like(ex3)
+        de3 = lambda t: S.DEState(R3, NP3, NP3, D3 * NP3, 13, t, x3.data_ptr(), ex3.data_ptr(),  # noqa: E731
+                                  u3.data_ptr(), eu3.data_ptr(), 0, 0)
+        ctx.de_step(prob3, 0, de3(0), 0.5, 0.9, stream=st)
+        ms_de3 = timed_calls(lambda t: ctx.de_step(prob3, 0, de3(t), 0.5, 0.9, stream=st), 1)
+        del x3, u3, ex3, eu3
         v = torch.empty_like(x); p = torch.empty_like(x)
         ep = torch.empty(n, device="cuda"); gb = torch.zeros(R, dtype=torch.int32, device="cuda")
         ps = lambda t: S.PSOState(R, NP, NP, D * NP, 9, t, x.data_ptr(), v.data_ptr(),  # noqa: E731
@@ -601,6 +619,9 @@ def run_workload(a):
               de_np200={"evals_per_s": round(n2 / (ms_de2 / 1e3), 1), "ms": round(ms_de2, 4),
                         "achieved_gbs": round(n2 * (12 * D + 12) / (ms_de2 / 1e3) / 1e9, 1),
                         "note": "10240 populations x 200 at D=30 (donors gathered from LDS)"},
+              de_np200_d100={"evals_per_s": round(n3 / (ms_de3 / 1e3), 1), "ms": round(ms_de3, 4),
+                             "achieved_gbs": round(n3 * (12 * D3 + 12) / (ms_de3 / 1e3) / 1e9, 1),
+                             "note": "4096 populations x 200 at D=100, C4's largest (staged in slabs of rows)"},
               pso={"evals_per_s": round(n / (ms_pso / 1e3), 1), "ms": round(ms_pso, 4),
                    "achieved_gbs": round(gbs_pso, 1), "frac": round(gbs_pso / PEAK_HBM_GBS, 4),
                    "algorithmic_bytes": b_pso},

@@ -32,8 +32,9 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
 // Persistent grid: the tiles (64*CT points each) of all items of one call are
 // numbered consecutively, item after item; workgroup L walks the contiguous
 // range [L T / G, (L + 1) T / G).  The rotation of an item is staged in LDS
-// when the walk enters the item, and each wave loads the coordinates of its
-// next tile while the current one is rotated and reduced.  Logical
+// when the walk enters the item, after the loads of the wave's first tile
+// have been issued; each wave's loads of its next tile are in flight while
+// the current one is shifted, rotated and reduced.  Logical
 // workgroups are renumbered per XCD, so an XCD works through a contiguous
 // stretch of items and their rotations stay in that XCD's L2.
 template <int KS, int CT>
@@ -57,36 +58,40 @@ __global__ __launch_bounds__(256, CT == 1 ? 3 : 2) void k_eval_small(const EvalD
     int cur = -1;
     const EvalDesc *it = nullptr;
     float b[KS][CT], bn[KS][CT];
-    bool have_next = false;
+    bool have_next = false;   // bn holds the raw coordinates of tile g
     for (int g = tb; g < te; ++g) {
         const int item = tile_item[g];
-        if (item != cur) {
-            __syncthreads();   // every wave is done with the previous item's LDS
-            cur = item;
-            it = items + item;
-            const SEVO_GLOBAL double *og = gin<double>(it->o);
-            const SEVO_GLOBAL float *tg = gin<float>(it->tab);
-            stage_rotation<KS>(sA, it->Mfrag);
-            for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
-            for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
-            __syncthreads();
-            have_next = false;
-        }
-        const int dim = it->dim, n = it->n;
-        const int64_t ld = it->ld;
-        const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
-        SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
-        const int p0 = (g - it->block0) * TILE + wave * 16 * CT;
+        const EvalDesc *ig = items + item;
+        const int p0 = (g - ig->block0) * TILE + wave * 16 * CT;
         if (have_next) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                 for (int c = 0; c < CT; ++c) b[ks][c] = bn[ks][c];
         } else {
-            load_b<KS, CT>(b, X, ld, dim, n, p0, kq, pc, sO);
+            // the tile's loads go out before the item's rotation is staged,
+            // so that the two latencies overlap
+            load_raw<KS, CT>(b, gin<float>(ig->x), ig->ld, ig->dim, ig->n, p0, kq, pc);
         }
+        if (item != cur) {
+            __syncthreads();   // every wave is done with the previous item's LDS
+            cur = item;
+            it = ig;
+            const SEVO_GLOBAL double *og = gin<double>(it->o);
+            const SEVO_GLOBAL float *tg = gin<float>(it->tab);
+            stage_rotation<KS>(sA, it->Mfrag);
+            for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
+            for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
+            __syncthreads();
+        }
+        const int dim = it->dim, n = it->n;
+        const int64_t ld = it->ld;
+        const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
+        SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
+        shift_raw<KS, CT>(b, dim, n, p0, kq, pc, sO);
+        // the next tile's loads stay in flight while this tile is computed
         have_next = g + 1 < te && tile_item[g + 1] == item;
-        if (have_next) load_b<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc, sO);
+        if (have_next) load_raw<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc);
         switch (it->func) {
         case ELLIPSOID: tile_body<ELLIPSOID, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
         case ROSENBROCK: tile_body<ROSENBROCK, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
@@ -126,36 +131,45 @@ __global__ __launch_bounds__(256, 2) void k_eval_small_bf16(const EvalDesc *__re
     int cur = -1;
     const EvalDesc *it = nullptr;
     float b[KS][CT], bn[KS][CT];
-    bool have_next = false;
+    bool have_next = false;   // bn holds the raw coordinates of tile g
     for (int g = tb; g < te; ++g) {
         const int item = tile_item[g];
-        if (item != cur) {
-            __syncthreads();   // every wave is done with the previous item's LDS
-            cur = item;
-            it = items + item;
-            const SEVO_GLOBAL double *og = gin<double>(it->o);
-            const SEVO_GLOBAL float *tg = gin<float>(it->tab);
-            stage_rotation_bf16<KS>(sAb, sAr, it->Mbf, it->Mfrag);
-            for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
-            for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
-            __syncthreads();
-            have_next = false;
-        }
-        const int dim = it->dim, n = it->n;
-        const int64_t ld = it->ld;
-        const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
-        SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
-        const int p0 = (g - it->block0) * TILE + wave * 16 * CT;
+        const EvalDesc *ig = items + item;
+        const int p0 = (g - ig->block0) * TILE + wave * 16 * CT;
         if (have_next) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                 for (int c = 0; c < CT; ++c) b[ks][c] = bn[ks][c];
         } else {
-            load_b<KS, CT>(b, X, ld, dim, n, p0, kq, pc, sO);
+            // the tile's loads go out before the item's rotation is staged
+            load_raw<KS, CT>(b, gin<float>(ig->x), ig->ld, ig->dim, ig->n, p0, kq, pc);
         }
+        if (item != cur) {
+            __syncthreads();   // every wave is done with the previous item's LDS
+            cur = item;
+            it = ig;
+            const SEVO_GLOBAL double *og = gin<double>(it->o);
+            const SEVO_GLOBAL float *tg = gin<float>(it->tab);
+            stage_rotation_bf16<KS>(sAb, sAr, it->Mbf, it->Mfrag);
+            for (int q = threadIdx.x; q < KS * 4; q += 256) sO[q] = q < it->dim ? og[q] : 0.0;
+            for (int q = threadIdx.x; q < RT * 16; q += 256) sT[q] = tg[q];
+            __syncthreads();
+        }
+        const int dim = it->dim, n = it->n;
+        const int64_t ld = it->ld;
+        const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
+        SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
+        if (!have_next) shift_raw<KS, CT>(b, dim, n, p0, kq, pc, sO);
+        // the next tile's coordinates are loaded and shifted before this tile
+        // is computed: holding them raw through the split and the MFMAs
+        // would take more registers than this kernel has (measured: 9 spilled,
+        // 117 against 108 us at D = 100)
         have_next = g + 1 < te && tile_item[g + 1] == item;
-        if (have_next) load_b<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc, sO);
+        if (have_next) {
+            load_raw<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc);
+            shift_raw<KS, CT>(bn, dim, n, p0 + TILE, kq, pc, sO);
+        }
         bf16x8 bt[3][SF][CT];
         split3_b<KS, CT>(bt, b);
         switch (it->func) {

@@ -32,6 +32,35 @@ __device__ __forceinline__ bool thread_run_ind(const StepGeom &g, int &r, int &i
     return true;
 }
 
+// LDS of the staged variation (k_de_variation_lds).  A population of at
+// most VAR_LDS_WHOLE bytes is staged whole (rows = dim, nothing else in LDS).
+// Otherwise the donors take 8 bytes per individual, followed by a slab of
+// rows x np values: a slab of at least 4 rows within 32 KB when possible
+// (four or more workgroups per CU), else within 64 KB.  0 rows: the
+// population does not fit (or np is beyond the 16-bit indices) and the
+// global gathers are used instead.
+constexpr size_t VAR_LDS_WHOLE = 48 * 1024, VAR_LDS_SMALL = 32 * 1024, VAR_LDS_MAX = 64 * 1024;
+
+__host__ __device__ inline size_t var_donor_bytes(int np) { return ((size_t)np * 8 + 15) & ~(size_t)15; }
+
+inline int var_slab_rows(int dim, int np, size_t tsize)
+{
+    if ((size_t)dim * np * tsize <= VAR_LDS_WHOLE) return dim;
+    if (np > 65535) return 0;
+    for (size_t budget : {VAR_LDS_SMALL, VAR_LDS_MAX}) {
+        const size_t d = var_donor_bytes(np);
+        if (d >= budget) continue;
+        const int rows = (int)((budget - d) / ((size_t)np * tsize)) / 4 * 4;
+        if (rows >= 4) return rows < dim ? rows : dim;
+    }
+    return 0;
+}
+
+inline size_t var_lds_bytes(int dim, int np, int rows, size_t tsize)
+{
+    return (rows < dim ? var_donor_bytes(np) : 0) + (size_t)rows * np * tsize;
+}
+
 // Generation 0: x uniform in the box (computed in double, stored as T).
 template <typename T>
 __global__ void k_init_pop(StepGeom g, double lb, double ub, T *__restrict__ x, T *__restrict__ v,
@@ -110,59 +139,81 @@ __global__ void k_de_variation(StepGeom g, T lb, T ub, T F, uint32_t thr, const 
 }
 
 // The same variation with the run's population staged in LDS, one workgroup
-// per run, for populations of at most VAR_LDS_BYTES: the donor gathers then
-// read LDS instead of one cache line per donor coordinate.  Same arithmetic,
-// same results.
-constexpr size_t VAR_LDS_BYTES = 48 * 1024;
-
-template <typename T>
+// per run, so that the donor gathers read LDS instead of one cache line per
+// donor coordinate.  The population passes through LDS in slabs of `rows`
+// coordinate rows (a multiple of 4, so that a crossover draw block never
+// straddles two slabs; every row at once when it fits), each loaded with
+// coalesced reads, and every individual's trial coordinates of the slab are
+// made from it.  The donors of each individual are drawn with the first
+// slab and, when there are more, kept in LDS as 16-bit indices.  Same draws,
+// same arithmetic, same results as k_de_variation.
+template <typename T, int STAGE_CH>
 __global__ __launch_bounds__(256) void k_de_variation_lds(StepGeom g, T lb, T ub, T F, uint32_t thr,
                                                           const T *__restrict__ x, T *__restrict__ u,
-                                                          int32_t *__restrict__ donors)
+                                                          int32_t *__restrict__ donors, int rows)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char sRaw[];
-    T *sX = reinterpret_cast<T *>(sRaw);   // [dim][np]
+    const bool slabs = rows < g.dim;   // the donors are kept for the later slabs
+    uint16_t *sD = reinterpret_cast<uint16_t *>(sRaw);                                  // [np][4]
+    T *sX = reinterpret_cast<T *>(sRaw + (slabs ? var_donor_bytes(g.np) : 0));         // [rows][np]
     const int r = blockIdx.x;
     const T *xr = x + (int64_t)r * g.rs;
     T *ur = u + (int64_t)r * g.rs;
+    const uint32_t uid = g.run_uid0 + (uint32_t)r;
     // staging in chunks of STAGE_CH elements per thread, all loads of a chunk
     // (clamped, so always valid) issued before its stores
-    constexpr int STAGE_CH = 8;
-    const int n = g.dim * g.np;
-    for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
-        T v[STAGE_CH];
+    for (int j0 = 0; j0 < g.dim; j0 += rows) {
+        const int nr = min(rows, g.dim - j0);
+        const int n = nr * g.np;
+        __syncthreads();   // the previous slab has been read and the donors written
+        for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
+            T v[STAGE_CH];
 #pragma unroll
-        for (int c = 0; c < STAGE_CH; ++c) {
-            const int q = min(q0 + c * 256, n - 1);
-            const int j = q / g.np, i = q - j * g.np;
-            v[c] = xr[(int64_t)j * g.ld + i];
+            for (int c = 0; c < STAGE_CH; ++c) {
+                const int q = min(q0 + c * 256, n - 1);
+                const int jj = q / g.np, i = q - jj * g.np;
+                v[c] = xr[(int64_t)(j0 + jj) * g.ld + i];
+            }
+#pragma unroll
+            for (int c = 0; c < STAGE_CH; ++c)
+                if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < g.np; i += 256) {
+            // donors drawn with the first slab, kept in LDS for the others
+            int r1, r2, r3, jrand;
+            if (j0 == 0) {
+                de_donors(uid, g.seed32, g.t, i, g.np, g.dim, r1, r2, r3, jrand);
+                if (slabs) {
+                    sD[4 * i] = (uint16_t)r1;
+                    sD[4 * i + 1] = (uint16_t)r2;
+                    sD[4 * i + 2] = (uint16_t)r3;
+                    sD[4 * i + 3] = (uint16_t)jrand;
+                }
+                if (donors) {
+                    int32_t *dn = donors + (int64_t)r * 4 * g.ld + i;
+                    dn[0] = r1;
+                    dn[g.ld] = r2;
+                    dn[2 * g.ld] = r3;
+                    dn[3 * g.ld] = jrand;
+                }
+            } else {
+                r1 = sD[4 * i];
+                r2 = sD[4 * i + 1];
+                r3 = sD[4 * i + 2];
+                jrand = sD[4 * i + 3];
+            }
+            for (int jj = 0; jj < nr; jj += 4) {
+                const u32x4 w = draw(uid, g.seed32, g.t, (uint32_t)i, TAG_CROSS, (uint32_t)((j0 + jj) >> 2));
 #pragma unroll
-        for (int c = 0; c < STAGE_CH; ++c)
-            if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
-    }
-    __syncthreads();
-    const uint32_t uid = g.run_uid0 + (uint32_t)r;
-    for (int i = threadIdx.x; i < g.np; i += 256) {
-        int r1, r2, r3, jrand;
-        de_donors(uid, g.seed32, g.t, i, g.np, g.dim, r1, r2, r3, jrand);
-        if (donors) {
-            int32_t *dn = donors + (int64_t)r * 4 * g.ld + i;
-            dn[0] = r1;
-            dn[g.ld] = r2;
-            dn[2 * g.ld] = r3;
-            dn[3 * g.ld] = jrand;
-        }
-        for (int jb = 0; jb * 4 < g.dim; ++jb) {
-            const u32x4 w = draw(uid, g.seed32, g.t, (uint32_t)i, TAG_CROSS, (uint32_t)jb);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = jb * 4 + e;
-                if (j >= g.dim) break;
-                const T *row = sX + j * g.np;
-                const T v = row[r1] + F * (row[r2] - row[r3]);
-                bool m;
-                ur[(int64_t)j * g.ld + i] = cross_repair<T>(word(w, e), thr, j, jrand, v, row[i], lb, ub, m);
+                for (int e = 0; e < 4; ++e) {
+                    if (jj + e >= nr) break;
+                    const int j = j0 + jj + e;
+                    const T *row = sX + (jj + e) * g.np;
+                    const T v = row[r1] + F * (row[r2] - row[r3]);
+                    bool m;
+                    ur[(int64_t)j * g.ld + i] = cross_repair<T>(word(w, e), thr, j, jrand, v, row[i], lb, ub, m);
+                }
             }
         }
     }
@@ -437,11 +488,21 @@ int de_step_t(sevo_ctx *ctx, const sevo_problem *prob, uint32_t inst, const sevo
         return eval_runs(ctx, prob, inst, st->n_runs, st->np, st->ld, st->run_stride, st->x, st->ex,
                          precision, s);
     }
-    const size_t pop_bytes = (size_t)prob->dim * st->np * sizeof(T);
-    if (pop_bytes <= VAR_LDS_BYTES)
-        hipLaunchKernelGGL(k_de_variation_lds<T>, dim3(st->n_runs), dim3(256), pop_bytes, s, g, (T)prob->lb,
+    const int rows = var_slab_rows(prob->dim, st->np, sizeof(T));
+    // a whole population takes little LDS, so many workgroups share a CU and
+    // short staging chunks (few registers) keep them resident; slabs of a
+    // large population stage in one memory round trip each (measured at D =
+    // 30: 2048 individuals 245 -> 206 us with 32-element chunks, 200
+    // individuals 144 -> 150 us)
+    const size_t lds = var_lds_bytes(prob->dim, st->np, rows, sizeof(T));
+    if (rows >= prob->dim)
+        hipLaunchKernelGGL((k_de_variation_lds<T, 8>), dim3(st->n_runs), dim3(256), lds, s, g, (T)prob->lb,
                            (T)prob->ub, (T)par->F, cr_threshold(par->CR), (const T *)st->x, (T *)st->u,
-                           st->donors);
+                           st->donors, rows);
+    else if (rows > 0)
+        hipLaunchKernelGGL((k_de_variation_lds<T, 128 / sizeof(T)>), dim3(st->n_runs), dim3(256), lds, s, g,
+                           (T)prob->lb, (T)prob->ub, (T)par->F, cr_threshold(par->CR), (const T *)st->x,
+                           (T *)st->u, st->donors, rows);
     else
         hipLaunchKernelGGL(k_de_variation<T>, dim3(nb), dim3(256), 0, s, g, (T)prob->lb, (T)prob->ub,
                            (T)par->F, cr_threshold(par->CR), (const T *)st->x, (T *)st->u, st->donors);

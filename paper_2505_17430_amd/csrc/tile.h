@@ -348,13 +348,4 @@ __device__ __forceinline__ void stage_rotation_bf16(bf16x8 *sAb, float *sAr, con
     }
 }
 
-template <int KS, int CT>
-__device__ __forceinline__ void load_b(float (&b)[KS][CT], const SEVO_GLOBAL float *__restrict__ X,
-                                       int64_t ld, int dim, int n, int p0, int kq, int pc,
-                                       const double *sO)
-{
-    load_raw<KS, CT>(b, X, ld, dim, n, p0, kq, pc);
-    shift_raw<KS, CT>(b, dim, n, p0, kq, pc, sO);
-}
-
 }  // namespace sevo

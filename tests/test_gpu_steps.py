@@ -65,7 +65,11 @@ class DEBufs:
         return buf.cpu().numpy()[r * self.ld: r * self.ld + self.np].astype(np.float64)
 
 
-@pytest.mark.parametrize("func,dim,np_", [(2, 10, 50), (0, 30, 37), (3, 7, 4), (1, 100, 200), (5, 2, 5)])
+# the variation stages a run's population in LDS: (10, 50) in one slab,
+# (100, 200) in three slabs of at most 36 rows, (30, 2048) in eight slabs of
+# 4 rows; (13, 4096) does not fit and gathers its donors from global memory
+@pytest.mark.parametrize("func,dim,np_", [(2, 10, 50), (0, 30, 37), (3, 7, 4), (1, 100, 200), (5, 2, 5),
+                                          (2, 30, 2048), (4, 13, 4096)])
 def test_de_steps_parity(ctx, func, dim, np_):
     R, uid0, F, CR = 3, 40, 0.5, 0.9
     o, M = O.instance(func, dim, 0, ISEED)
