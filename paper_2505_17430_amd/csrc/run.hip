@@ -262,14 +262,32 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
         G.cost.push_back((double)d.budget * R.dim * R.dim);
         if (onchip[r]) G.stride = std::max(G.stride, dyn[r]);
     }
-    // the groups run concurrently, one internal stream each (a plan records
-    // the stream index and forks when it is launched)
-    const bool recording = ctx_recording(ctx) != nullptr;
-    const int ng = (int)groups.size();
-    std::vector<hipStream_t> ss(ng, stream);
-    if (!recording && (rc = fork_streams(ctx, stream, ng, ss.data()))) return rc;
-    int g = 0;
-    for (auto &kv : groups) {
+    // Launch order and streams.  Groups go longest run first.  A group
+    // whose workgroups fill every slot the GPU holds for its kernel runs
+    // alone: such groups follow one another on the caller's stream, since
+    // beside another group part of its workgroups would wait for a slot and
+    // finish a whole run length late (measured: 2048 L-SHADE runs at
+    // D = 10, 30, 50, 100, 1.39 s one class after another against 1.89 s
+    // together).  Smaller groups get an internal stream each and run beside
+    // the others (4096 PSO swarms in three classes of 360 workgroups:
+    // 105 ms together against 139 ms).  A plan records each launch's stream index
+    // and forks when it is launched.  SEVO_RUN_GROUPS=serial|concurrent
+    // forces one way for all groups.
+    struct Prepared {
+        std::vector<RunDev> launch;
+        unsigned grid;
+        bool on, wave;
+        int key;
+        size_t stride;
+        int lane;
+    };
+    std::vector<std::pair<double, std::map<int, Group>::iterator>> byc;
+    for (auto itg = groups.begin(); itg != groups.end(); ++itg)
+        byc.emplace_back(*std::max_element(itg->second.cost.begin(), itg->second.cost.end()), itg);
+    std::stable_sort(byc.begin(), byc.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<Prepared> prep;
+    for (auto &bc : byc) {
+        auto &kv = *bc.second;
         const bool gon = (kv.first & 2) != 0, gwave = (kv.first & 1) != 0;
         Group &G = kv.second;
         std::vector<RunDev> launch;
@@ -306,19 +324,43 @@ int run_fused(sevo_ctx *ctx, const sevo_run_desc *runs, int n, sevo_run_result *
                 }
         }
         const unsigned grid = (unsigned)(gwave ? launch.size() / 4 : launch.size());
-        std::vector<char> blob(launch.size() * sizeof(RunDev));
-        std::memcpy(blob.data(), launch.data(), blob.size());
+        prep.push_back({std::move(launch), grid, gon, gwave, kv.first, G.stride, 0});
+    }
+    const char *gm = std::getenv("SEVO_RUN_GROUPS");
+    const bool all_serial = gm && std::strcmp(gm, "serial") == 0;
+    const bool all_conc = gm && std::strcmp(gm, "concurrent") == 0;
+    int ng = 1;   // lane 0: the caller's stream, for the groups that run alone
+    for (auto &P : prep) {
+        bool alone = all_serial;
+        if (!all_serial && !all_conc) {
+            int per_cu = 0;
+            const size_t shm = P.on ? (P.wave ? 4 : 1) * P.stride * sizeof(float) : 0;
+            RunKernel k = run_table(P.key / 4 % NFAM, P.key / 4 / NFAM, P.on, P.wave);
+            if (k && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, shm) == hipSuccess && per_cu > 0)
+                alone = (long)P.grid >= (long)per_cu * cus;
+            (void)hipGetLastError();
+        }
+        P.lane = alone ? 0 : ng++;
+    }
+    const bool recording = ctx_recording(ctx) != nullptr;
+    std::vector<hipStream_t> ss(ng, stream);
+    if (!recording && ng > 1) {
+        if ((rc = fork_streams(ctx, stream, ng - 1, ss.data() + 1))) return rc;
+    }
+    for (auto &P : prep) {
+        const int g = P.lane;
+        std::vector<char> blob(P.launch.size() * sizeof(RunDev));
+        std::memcpy(blob.data(), P.launch.data(), blob.size());
         const void *d = nullptr;
         int slot;
         if ((rc = stage_blob(ctx, blob, ss[g], &d, &slot))) return rc;
-        const size_t shm = gon ? (gwave ? 4 : 1) * G.stride * sizeof(float) : 0;
-        const Launch L{L_RUN, d, (int)launch.size(), kv.first / 4 / NFAM, 0, (int)grid, gon, gwave, shm,
-                       (int)G.stride, g, kv.first / 4 % NFAM};
+        const size_t shm = P.on ? (P.wave ? 4 : 1) * P.stride * sizeof(float) : 0;
+        const Launch L{L_RUN, d, (int)P.launch.size(), P.key / 4 / NFAM, 0, (int)P.grid, P.on, P.wave, shm,
+                       (int)P.stride, g, P.key / 4 % NFAM};
         if ((rc = emit_launch(ctx, L, ss[g]))) return rc;
         if ((rc = finish_slot(ctx, slot, ss[g]))) return rc;
-        ++g;
     }
-    return recording ? SEVO_OK : join_streams(ctx, stream, ng, ss.data());
+    return recording || ng == 1 ? SEVO_OK : join_streams(ctx, stream, ng - 1, ss.data() + 1);
 }
 
 // Single-precision runs: the fused kernels for DE, SHADE, L-SHADE, PSO and
