@@ -208,7 +208,6 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
     const int kq = lane >> 4, pc = lane & 15;
     const int RT = (dim + 15) / 16, KS = (dim + 3) / 4, K32 = (dim + 31) / 32;
     const int rt0 = rb * 8 + w * 2;
-    const bool act0 = rt0 < RT, act1 = rt0 + 1 < RT;
     const SEVO_GLOBAL float *Mf = gin<float>(it.Mfrag);
     const SEVO_GLOBAL float *tab = gin<float>(it.tab);
 
@@ -235,29 +234,25 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         const int s0 = (v0 >> 2) * SK + (v0 & 3) * 8, s1 = (v1 >> 2) * SK + (v1 & 3) * 8;
         const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
         const int64_t mblock = (int64_t)RT * K32 * 512;   // bf16 per term block of M
-        const int rt1 = act1 ? rt0 + 1 : rt0;
-        // a[r][t]: term t of row tile r's fragment of chunk kk
-        auto load_a = [&](int kk, bf16x8 (&a)[2][3]) {
-            const int64_t i0 = (((int64_t)min(rt0, RT - 1) * K32 + kk) * 64 + lane) * 8;
-            const int64_t i1 = (((int64_t)min(rt1, RT - 1) * K32 + kk) * 64 + lane) * 8;
+        // a[r][t]: term t of row tile r's fragment of chunk kk, as raw words.
+        // Row tiles past the matrix (in the last row block) load the last
+        // real row tile again: their rows lie past dim, so the fold discards
+        // them, and the MFMAs run unconditionally with nothing computed on
+        // the fragments between their loads and their use (a select there
+        // made the compiler wait for the next chunk's loads before this
+        // chunk's MFMAs).
+        const int rc0 = min(rt0, RT - 1), rc1 = min(rt0 + 1, RT - 1);
+        auto load_a = [&](int kk, vu32x4 (&a)[2][3]) {
+            const int64_t i0 = (((int64_t)rc0 * K32 + kk) * 64 + lane) * 8;
+            const int64_t i1 = (((int64_t)rc1 * K32 + kk) * 64 + lane) * 8;
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
-                a[0][t] = *(const SEVO_GLOBAL bf16x8 *)(Mh + t * mblock + i0);
-                a[1][t] = *(const SEVO_GLOBAL bf16x8 *)(Mh + t * mblock + i1);
+                a[0][t] = *(const SEVO_GLOBAL vu32x4 *)(Mh + t * mblock + i0);
+                a[1][t] = *(const SEVO_GLOBAL vu32x4 *)(Mh + t * mblock + i1);
             }
         };
-        // M fragments of row tiles past the matrix are zeroed where they are
-        // loaded, so that the MFMAs run unconditionally (a branch around them
-        // makes the compiler copy the accumulators every iteration) and read
-        // no register whose load may still be in flight at the loop head
-        // (that would make it wait for the prefetch loads in the loop)
-        bf16x8 a[2][3];
+        vu32x4 a[2][3];
         load_a(0, a);
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            if (!act0) a[0][t] = bf16x8{};
-            if (!act1) a[1][t] = bf16x8{};
-        }
         vu32x4 b0[3], b1[3];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -270,9 +265,14 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
             *reinterpret_cast<vu32x4 *>(sBt[t] + s1) = b1[t];
         }
         __syncthreads();
+        // every global load of the prologue is complete here; without this
+        // wait the compiler's bookkeeping of the fragments loaded before the
+        // loop makes each iteration wait for all loads in flight, the next
+        // chunk's prefetch included (vmcnt 0; expcnt and lgkmcnt unconstrained)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         for (int kk = 0; kk < K32; ++kk) {
             const bool more = kk + 1 < K32;
-            bf16x8 na[2][3];
+            vu32x4 na[2][3];
             if (more) {
                 const int64_t d = (int64_t)(kk + 1) * 512;
 #pragma unroll
@@ -290,14 +290,17 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBt[2] + off);
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, a[r][0]);
+                    const bf16x8 am = __builtin_bit_cast(bf16x8, a[r][1]);
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, a[r][2]);
                     // smallest products first, so the float accumulation
                     // loses the least of them
-                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][1], bm, z[r][c], 0, 0, 0);
-                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][2], bh, z[r][c], 0, 0, 0);
-                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][0], bl, z[r][c], 0, 0, 0);
-                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][1], bh, z[r][c], 0, 0, 0);
-                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][0], bm, z[r][c], 0, 0, 0);
-                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r][0], bh, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, z[r][c], 0, 0, 0);
+                    z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, z[r][c], 0, 0, 0);
                 }
             }
             __syncthreads();
@@ -306,8 +309,8 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 for (int t = 0; t < 3; ++t) {
                     *reinterpret_cast<vu32x4 *>(sBt[t] + s0) = b0[t];
                     *reinterpret_cast<vu32x4 *>(sBt[t] + s1) = b1[t];
-                    a[0][t] = act0 ? na[0][t] : bf16x8{};
-                    a[1][t] = act1 ? na[1][t] : bf16x8{};
+                    a[0][t] = na[0][t];
+                    a[1][t] = na[1][t];
                 }
             }
             __syncthreads();
@@ -326,11 +329,11 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
             const int v = threadIdx.x + 256 * j;
             sv[j] = (v >> 5) * SB + (v & 31) * 4;
         }
-        const int rt1 = act1 ? rt0 + 1 : rt0;
         const int64_t m0 = (int64_t)min(rt0, RT - 1) * KS * 64 + lane;
-        const int64_t m1 = (int64_t)min(rt1, RT - 1) * KS * 64 + lane;
+        const int64_t m1 = (int64_t)min(rt0 + 1, RT - 1) * KS * 64 + lane;
         // k-steps past the matrix read the last one (their operand rows are
-        // zero); row tiles past the matrix get zero fragments
+        // zero); row tiles past the matrix read the last real one, as in the
+        // split path (the fold discards their rows)
         auto load_a = [&](int kk, float (&a0)[KC / 4], float (&a1)[KC / 4]) {
 #pragma unroll
             for (int ks = 0; ks < KC / 4; ++ks) {
@@ -345,13 +348,13 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[j] = Bf[g0 + 256 * j];
 #pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks) {
-            a0[ks] = act0 ? a0[ks] : 0.f;
-            a1[ks] = act1 ? a1[ks] : 0.f;
-        }
-#pragma unroll
         for (int j = 0; j < 4; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
         __syncthreads();
+        // every global load of the prologue is complete here; without this
+        // wait the compiler's bookkeeping of the fragments loaded before the
+        // loop makes each iteration wait for all loads in flight, the next
+        // chunk's prefetch included (vmcnt 0; expcnt and lgkmcnt unconstrained)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         for (int kk = 0; kk < K32; ++kk) {
             const bool more = kk + 1 < K32;
             float n0[KC / 4], n1[KC / 4];
@@ -361,13 +364,21 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 for (int j = 0; j < 4; ++j) b[j] = Bf[g0 + d + 256 * j];
                 load_a(kk + 1, n0, n1);
             }
+            // the points of k-step ks + 1 are read from LDS while the MFMAs
+            // of k-step ks run
+            float bv[2][CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) bv[0][c] = sB[kq * SB + c * 16 + pc];
 #pragma unroll
             for (int ks = 0; ks < KC / 4; ++ks) {
+                if (ks + 1 < KC / 4) {
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) bv[(ks + 1) & 1][c] = sB[((ks + 1) * 4 + kq) * SB + c * 16 + pc];
+                }
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
-                    const float bv = sB[(ks * 4 + kq) * SB + c * 16 + pc];
-                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv, z[0][c], 0, 0, 0);
-                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, z[1][c], 0, 0, 0);
+                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv[ks & 1][c], z[0][c], 0, 0, 0);
+                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv[ks & 1][c], z[1][c], 0, 0, 0);
                 }
             }
             __syncthreads();
@@ -376,8 +387,8 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 for (int j = 0; j < 4; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
 #pragma unroll
                 for (int ks = 0; ks < KC / 4; ++ks) {
-                    a0[ks] = act0 ? n0[ks] : 0.f;
-                    a1[ks] = act1 ? n1[ks] : 0.f;
+                    a0[ks] = n0[ks];
+                    a1[ks] = n1[ks];
                 }
             }
             __syncthreads();
