@@ -147,7 +147,7 @@ __global__ void k_de_variation(StepGeom g, T lb, T ub, T F, uint32_t thr, const 
 // made from it.  The donors of each individual are drawn with the first
 // slab and, when there are more, kept in LDS as 16-bit indices.  Same draws,
 // same arithmetic, same results as k_de_variation.
-template <typename T, int STAGE_CH>
+template <typename T, int STAGE_CH, bool FLAT>
 __global__ __launch_bounds__(256) void k_de_variation_lds(StepGeom g, T lb, T ub, T F, uint32_t thr,
                                                           const T *__restrict__ x, T *__restrict__ u,
                                                           int32_t *__restrict__ donors, int rows)
@@ -160,23 +160,44 @@ __global__ __launch_bounds__(256) void k_de_variation_lds(StepGeom g, T lb, T ub
     const T *xr = x + (int64_t)r * g.rs;
     T *ur = u + (int64_t)r * g.rs;
     const uint32_t uid = g.run_uid0 + (uint32_t)r;
-    // staging in chunks of STAGE_CH elements per thread, all loads of a chunk
-    // (clamped, so always valid) issued before its stores
     for (int j0 = 0; j0 < g.dim; j0 += rows) {
         const int nr = min(rows, g.dim - j0);
         const int n = nr * g.np;
         __syncthreads();   // the previous slab has been read and the donors written
-        for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
-            T v[STAGE_CH];
+        if constexpr (FLAT) {
+            // a whole population with ld = np and a 16-byte aligned start
+            // (the host checks) is one contiguous array: 16-byte vectors, all
+            // loads of a chunk of STAGE_CH per thread before their stores,
+            // then the elements after the last whole vector
+            typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+            constexpr int VW = 16 / sizeof(T);
+            const int nv = n / VW;
+            const u32x4v *xv = reinterpret_cast<const u32x4v *>(xr);
+            u32x4v *sv = reinterpret_cast<u32x4v *>(sX);
+            for (int q0 = threadIdx.x; q0 < nv; q0 += 256 * STAGE_CH) {
+                u32x4v v[STAGE_CH];
 #pragma unroll
-            for (int c = 0; c < STAGE_CH; ++c) {
-                const int q = min(q0 + c * 256, n - 1);
-                const int jj = q / g.np, i = q - jj * g.np;
-                v[c] = xr[(int64_t)(j0 + jj) * g.ld + i];
+                for (int c = 0; c < STAGE_CH; ++c) v[c] = xv[min(q0 + c * 256, nv - 1)];
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c)
+                    if (q0 + c * 256 < nv) sv[q0 + c * 256] = v[c];
             }
+            for (int q = nv * VW + (int)threadIdx.x; q < n; q += 256) sX[q] = xr[q];
+        } else {
+            // staging in chunks of STAGE_CH elements per thread, all loads of
+            // a chunk (clamped, so always valid) issued before its stores
+            for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
+                T v[STAGE_CH];
 #pragma unroll
-            for (int c = 0; c < STAGE_CH; ++c)
-                if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
+                for (int c = 0; c < STAGE_CH; ++c) {
+                    const int q = min(q0 + c * 256, n - 1);
+                    const int jj = q / g.np, i = q - jj * g.np;
+                    v[c] = xr[(int64_t)(j0 + jj) * g.ld + i];
+                }
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c)
+                    if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
+            }
         }
         __syncthreads();
         for (int i = threadIdx.x; i < g.np; i += 256) {
@@ -495,12 +516,20 @@ int de_step_t(sevo_ctx *ctx, const sevo_problem *prob, uint32_t inst, const sevo
     // 30: 2048 individuals 245 -> 206 us with 32-element chunks, 200
     // individuals 144 -> 150 us)
     const size_t lds = var_lds_bytes(prob->dim, st->np, rows, sizeof(T));
-    if (rows >= prob->dim)
-        hipLaunchKernelGGL((k_de_variation_lds<T, 8>), dim3(st->n_runs), dim3(256), lds, s, g, (T)prob->lb,
-                           (T)prob->ub, (T)par->F, cr_threshold(par->CR), (const T *)st->x, (T *)st->u,
-                           st->donors, rows);
+    // a whole dense population (ld = np) whose runs start on 16-byte
+    // boundaries stages as one contiguous array of 16-byte vectors
+    const bool flat = rows >= prob->dim && st->ld == st->np && (st->run_stride * sizeof(T)) % 16 == 0 &&
+                      ((uintptr_t)st->x) % 16 == 0;
+    if (flat)
+        hipLaunchKernelGGL((k_de_variation_lds<T, 8, true>), dim3(st->n_runs), dim3(256), lds, s, g,
+                           (T)prob->lb, (T)prob->ub, (T)par->F, cr_threshold(par->CR), (const T *)st->x,
+                           (T *)st->u, st->donors, rows);
+    else if (rows >= prob->dim)
+        hipLaunchKernelGGL((k_de_variation_lds<T, 8, false>), dim3(st->n_runs), dim3(256), lds, s, g,
+                           (T)prob->lb, (T)prob->ub, (T)par->F, cr_threshold(par->CR), (const T *)st->x,
+                           (T *)st->u, st->donors, rows);
     else if (rows > 0)
-        hipLaunchKernelGGL((k_de_variation_lds<T, 128 / sizeof(T)>), dim3(st->n_runs), dim3(256), lds, s, g,
+        hipLaunchKernelGGL((k_de_variation_lds<T, 128 / sizeof(T), false>), dim3(st->n_runs), dim3(256), lds, s, g,
                            (T)prob->lb, (T)prob->ub, (T)par->F, cr_threshold(par->CR), (const T *)st->x,
                            (T *)st->u, st->donors, rows);
     else
