@@ -67,13 +67,17 @@ class DEBufs:
 
 # the variation stages a run's population in LDS: (10, 50) in one slab,
 # (100, 200) in three slabs of at most 36 rows, (30, 2048) in eight slabs of
-# 4 rows; (13, 4096) does not fit and gathers its donors from global memory
-@pytest.mark.parametrize("func,dim,np_", [(2, 10, 50), (0, 30, 37), (3, 7, 4), (1, 100, 200), (5, 2, 5),
-                                          (2, 30, 2048), (4, 13, 4096)])
-def test_de_steps_parity(ctx, func, dim, np_):
+# 4 rows; (13, 4096) does not fit and gathers its donors from global memory.
+# With ld = np and runs on 16-byte boundaries (pad 0, run stride a multiple
+# of 4 floats) a whole population stages as 16-byte vectors: (10, 50) with
+# no tail, (7, 5) with 35 elements, three after the last whole vector.
+@pytest.mark.parametrize("func,dim,np_,pad,rpad", [(2, 10, 50, 3, 5), (0, 30, 37, 3, 5), (3, 7, 4, 3, 5),
+                                                   (1, 100, 200, 3, 5), (5, 2, 5, 3, 5), (2, 30, 2048, 3, 5),
+                                                   (4, 13, 4096, 3, 5), (2, 10, 50, 0, 0), (0, 7, 5, 0, 1)])
+def test_de_steps_parity(ctx, func, dim, np_, pad, rpad):
     R, uid0, F, CR = 3, 40, 0.5, 0.9
     o, M = O.instance(func, dim, 0, ISEED)
-    b = DEBufs(R, np_, dim)
+    b = DEBufs(R, np_, dim, pad=pad, rpad=rpad)
     prob = S.problem(func, dim)
     say(f"  de func={func} dim={dim} np={np_} t=0")
     ctx.de_step(prob, 0, b.state(0, uid0), F, CR)
