@@ -447,7 +447,9 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
     }
     __syncthreads();
 
-    const RunDev R = runs[run_index];
+    // read in place (scalar loads where it is used), not copied: a copy held
+    // the whole descriptor in registers and made the larger kernels spill
+    const RunDev &R = runs[run_index];
     if (WAVE && R.np == 0) return;   // empty slot: no barrier follows for wave teams
     const int D = R.dim, npp = R.npp;
     int np = R.np;   // L-SHADE shrinks it
