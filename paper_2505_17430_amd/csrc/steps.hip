@@ -160,46 +160,11 @@ __global__ __launch_bounds__(256) void k_de_variation_lds(StepGeom g, T lb, T ub
     const T *xr = x + (int64_t)r * g.rs;
     T *ur = u + (int64_t)r * g.rs;
     const uint32_t uid = g.run_uid0 + (uint32_t)r;
-    for (int j0 = 0; j0 < g.dim; j0 += rows) {
-        const int nr = min(rows, g.dim - j0);
-        const int n = nr * g.np;
-        __syncthreads();   // the previous slab has been read and the donors written
-        if constexpr (FLAT) {
-            // a whole population with ld = np and a 16-byte aligned start
-            // (the host checks) is one contiguous array: 16-byte vectors, all
-            // loads of a chunk of STAGE_CH per thread before their stores,
-            // then the elements after the last whole vector
-            typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
-            constexpr int VW = 16 / sizeof(T);
-            const int nv = n / VW;
-            const u32x4v *xv = reinterpret_cast<const u32x4v *>(xr);
-            u32x4v *sv = reinterpret_cast<u32x4v *>(sX);
-            for (int q0 = threadIdx.x; q0 < nv; q0 += 256 * STAGE_CH) {
-                u32x4v v[STAGE_CH];
-#pragma unroll
-                for (int c = 0; c < STAGE_CH; ++c) v[c] = xv[min(q0 + c * 256, nv - 1)];
-#pragma unroll
-                for (int c = 0; c < STAGE_CH; ++c)
-                    if (q0 + c * 256 < nv) sv[q0 + c * 256] = v[c];
-            }
-            for (int q = nv * VW + (int)threadIdx.x; q < n; q += 256) sX[q] = xr[q];
-        } else {
-            // staging in chunks of STAGE_CH elements per thread, all loads of
-            // a chunk (clamped, so always valid) issued before its stores
-            for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
-                T v[STAGE_CH];
-#pragma unroll
-                for (int c = 0; c < STAGE_CH; ++c) {
-                    const int q = min(q0 + c * 256, n - 1);
-                    const int jj = q / g.np, i = q - jj * g.np;
-                    v[c] = xr[(int64_t)(j0 + jj) * g.ld + i];
-                }
-#pragma unroll
-                for (int c = 0; c < STAGE_CH; ++c)
-                    if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
-            }
-        }
-        __syncthreads();
+    // q / np for the staging indices (q < 2^16): the product with
+    // ceil(2^32 / np), high word, is exact there
+    const uint32_t inv_np = (uint32_t)(0xFFFFFFFFull / (uint32_t)g.np) + 1u;
+    // the mutants and crossover of slab rows [j0, j0 + nr), from sX
+    auto compute = [&](int j0, int nr) {
         for (int i = threadIdx.x; i < g.np; i += 256) {
             // donors drawn with the first slab, kept in LDS for the others
             int r1, r2, r3, jrand;
@@ -237,6 +202,79 @@ __global__ __launch_bounds__(256) void k_de_variation_lds(StepGeom g, T lb, T ub
                 }
             }
         }
+    };
+    // element q of the slab at row j0 (clamped, so always a valid address)
+    auto slab_elem = [&](int j0, int n, int q) {
+        q = min(q, n - 1);
+        const int jj = (int)__umulhi((uint32_t)q, inv_np), i = q - jj * g.np;
+        return xr[(int64_t)(j0 + jj) * g.ld + i];
+    };
+    if (!FLAT && slabs && rows * g.np <= 256 * STAGE_CH) {
+        // a slab is one chunk per thread: the next slab's loads are issued
+        // before this slab is computed and stored to LDS after it
+        T v[STAGE_CH];
+        int n = min(rows, g.dim) * g.np;
+#pragma unroll
+        for (int c = 0; c < STAGE_CH; ++c) v[c] = slab_elem(0, n, threadIdx.x + c * 256);
+#pragma unroll
+        for (int c = 0; c < STAGE_CH; ++c)
+            if ((int)threadIdx.x + c * 256 < n) sX[threadIdx.x + c * 256] = v[c];
+        for (int j0 = 0; j0 < g.dim; j0 += rows) {
+            __syncthreads();   // slab j0 is in LDS
+            const int nr = min(rows, g.dim - j0);
+            const bool more = j0 + rows < g.dim;
+            if (more) {
+                n = min(rows, g.dim - j0 - rows) * g.np;
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c) v[c] = slab_elem(j0 + rows, n, threadIdx.x + c * 256);
+            }
+            compute(j0, nr);
+            __syncthreads();   // slab j0 has been read and the donors written
+            if (more) {
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c)
+                    if ((int)threadIdx.x + c * 256 < n) sX[threadIdx.x + c * 256] = v[c];
+            }
+        }
+        return;
+    }
+    for (int j0 = 0; j0 < g.dim; j0 += rows) {
+        const int nr = min(rows, g.dim - j0);
+        const int n = nr * g.np;
+        __syncthreads();   // the previous slab has been read and the donors written
+        if constexpr (FLAT) {
+            // a whole population with ld = np and a 16-byte aligned start
+            // (the host checks) is one contiguous array: 16-byte vectors, all
+            // loads of a chunk of STAGE_CH per thread before their stores,
+            // then the elements after the last whole vector
+            typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+            constexpr int VW = 16 / sizeof(T);
+            const int nv = n / VW;
+            const u32x4v *xv = reinterpret_cast<const u32x4v *>(xr);
+            u32x4v *sv = reinterpret_cast<u32x4v *>(sX);
+            for (int q0 = threadIdx.x; q0 < nv; q0 += 256 * STAGE_CH) {
+                u32x4v v[STAGE_CH];
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c) v[c] = xv[min(q0 + c * 256, nv - 1)];
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c)
+                    if (q0 + c * 256 < nv) sv[q0 + c * 256] = v[c];
+            }
+            for (int q = nv * VW + (int)threadIdx.x; q < n; q += 256) sX[q] = xr[q];
+        } else {
+            // staging in chunks of STAGE_CH elements per thread, all loads of
+            // a chunk issued before its stores
+            for (int q0 = threadIdx.x; q0 < n; q0 += 256 * STAGE_CH) {
+                T v[STAGE_CH];
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c) v[c] = slab_elem(j0, n, q0 + c * 256);
+#pragma unroll
+                for (int c = 0; c < STAGE_CH; ++c)
+                    if (q0 + c * 256 < n) sX[q0 + c * 256] = v[c];
+            }
+        }
+        __syncthreads();
+        compute(j0, nr);
     }
 }
 
