@@ -761,8 +761,9 @@ __global__ __launch_bounds__(256, 2) void k_run(const RunDev *__restrict__ runs,
                 }
             }
             t.sync();
-            // chunks of DE_CH coordinate blocks, loads before stores (see PSO)
-            constexpr int DE_CH = ONCHIP ? 1 : (KS <= 13 ? 2 : 1);
+            // chunks of DE_CH coordinate blocks, loads before stores (see PSO);
+            // two blocks fit the registers of every workspace variant
+            constexpr int DE_CH = ONCHIP ? 1 : 2;
             const int nb4 = (D + 3) / 4;
             for (int jb0 = wave * DE_CH; jb0 < nb4; jb0 += NW * DE_CH)
                 for (int i = lane; i < np; i += 64) {
