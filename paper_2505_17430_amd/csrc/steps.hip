@@ -369,26 +369,48 @@ __global__ __launch_bounds__(256) void k_pso_best(StepGeom g, int init, const T 
     __shared__ int si[256];
     T bv = T(INFINITY);
     int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < g.np; i += 256) {
-        const int64_t e_at = (int64_t)r * g.ld + i;
-        if (init || err_key(ex[e_at]) < err_key(ep[e_at])) {
-            ep[e_at] = ex[e_at];
-            if (!init) {
-                // chunks of 8 coordinates, loads before stores
-                constexpr int CP_CH = 8;
-                const int64_t base = (int64_t)r * g.rs + i;
-                for (int j0 = 0; j0 < g.dim; j0 += CP_CH) {
-                    T v[CP_CH];
+    // passes of PB particles per thread: the errors of a pass are loaded
+    // together, then the improved particles' coordinates are copied in chunks
+    // of CP_CH coordinates, the loads of a chunk for all of them issued
+    // before its stores
+    constexpr int PB = 8, CP_CH = 8;
+    for (int i0 = threadIdx.x; i0 < g.np; i0 += 256 * PB) {
+        T kx[PB], kp[PB];
+        bool imp[PB];
 #pragma unroll
-                    for (int c = 0; c < CP_CH; ++c) v[c] = x[base + (int64_t)min(j0 + c, g.dim - 1) * g.ld];
+        for (int b = 0; b < PB; ++b) {
+            const int i = min(i0 + b * 256, g.np - 1);
+            const int64_t e_at = (int64_t)r * g.ld + i;
+            kx[b] = ex[e_at];
+            kp[b] = ep[e_at];
+        }
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int i = i0 + b * 256;
+            imp[b] = i < g.np && (init || err_key(kx[b]) < err_key(kp[b]));
+            if (imp[b]) {
+                ep[(int64_t)r * g.ld + i] = kx[b];
+                kp[b] = kx[b];
+            }
+            const T k = err_key(kp[b]);
+            if (i < g.np && (k < bv || (k == bv && i < bi))) { bv = k; bi = i; }
+        }
+        if (!init) {
+            const int64_t base = (int64_t)r * g.rs;
+            for (int j0 = 0; j0 < g.dim; j0 += CP_CH) {
+                T v[PB][CP_CH];
+#pragma unroll
+                for (int b = 0; b < PB; ++b)
 #pragma unroll
                     for (int c = 0; c < CP_CH; ++c)
-                        if (j0 + c < g.dim) p[base + (int64_t)(j0 + c) * g.ld] = v[c];
-                }
+                        v[b][c] = imp[b] ? x[base + (int64_t)min(j0 + c, g.dim - 1) * g.ld + i0 + b * 256] : T(0);
+#pragma unroll
+                for (int b = 0; b < PB; ++b)
+#pragma unroll
+                    for (int c = 0; c < CP_CH; ++c)
+                        if (imp[b] && j0 + c < g.dim) p[base + (int64_t)(j0 + c) * g.ld + i0 + b * 256] = v[b][c];
             }
         }
-        const T k = err_key(ep[e_at]);
-        if (k < bv || (k == bv && i < bi)) { bv = k; bi = i; }
     }
     sv[threadIdx.x] = bv;
     si[threadIdx.x] = bi;
