@@ -190,10 +190,12 @@ int sevo_evaluate_batch_noalloc(sevo_ctx *ctx, const sevo_eval_item *items, int3
 
 /* Autotuning of the batched evaluation (optional).  For every dimension
  * class (k-steps ceil(D/4), D <= 120) present in `items`, times the launch
- * shapes that cannot change any result -- the resident persistent grid and
- * 1, 2, 3, 4, 6 or 8 tiles of 64-128 points per workgroup -- on these items
- * (their err_out buffers are written, with the values sevo_evaluate_batch
- * gives), and keeps the fastest in the context for later calls.
+ * shapes that cannot change any result -- 1, 2, 3, 4, 6 or 8 tiles of
+ * 64-256 points per workgroup, and the resident persistent grid -- on these
+ * items (their err_out buffers are written, with the values
+ * sevo_evaluate_batch gives), and keeps in the context for later calls the
+ * first shape in that order whose time is within 2 % of the fastest (fewer
+ * tiles per workgroup move fewer bytes).
  *   chosen  optional host [64]: per class, the tiles per workgroup chosen
  *           (0 = resident grid), -1 for classes not present.
  * Synchronises `stream`.  FP64 has nothing to tune (returns 0). */
