@@ -89,8 +89,11 @@ __global__ __launch_bounds__(256, CT == 1 ? 3 : 2) void k_eval_small(const EvalD
         const SEVO_GLOBAL float *__restrict__ X = gin<float>(it->x);
         SEVO_GLOBAL float *__restrict__ E = gout<float>(it->err);
         shift_raw<KS, CT>(b, dim, n, p0, kq, pc, sO);
-        // the next tile's loads stay in flight while this tile is computed
-        have_next = g + 1 < te && tile_item[g + 1] == item;
+        // the next tile's loads stay in flight while this tile is computed,
+        // for the classes bound by memory (up to D = 32); above, the
+        // registers serve the rotation better (D = 100: 152 against 160
+        // VGPRs, 1 % faster) and the autotuner keeps one tile per workgroup
+        have_next = KS <= 8 && g + 1 < te && tile_item[g + 1] == item;
         if (have_next) load_raw<KS, CT>(bn, X, ld, dim, n, p0 + TILE, kq, pc);
         switch (it->func) {
         case ELLIPSOID: tile_body<ELLIPSOID, KS, CT>(b, sA, sT, lane, dim, n, p0, K.kf, E); break;
