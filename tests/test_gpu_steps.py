@@ -200,7 +200,10 @@ class PSOBufs:
         return buf.cpu().numpy()[r * self.ld: r * self.ld + self.np].astype(np.float64)
 
 
-@pytest.mark.parametrize("func,dim,np_", [(2, 10, 40), (4, 30, 40), (0, 50, 17), (3, 3, 1)])
+# the personal-best kernel takes eight particles per thread and pass: 600
+# particles fill part of a pass, 2100 need a second one
+@pytest.mark.parametrize("func,dim,np_", [(2, 10, 40), (4, 30, 40), (0, 50, 17), (3, 3, 1), (1, 6, 600),
+                                          (5, 4, 2100)])
 def test_pso_steps_parity(ctx, func, dim, np_):
     R, uid0 = 2, 100
     w, c1, c2, vmax = 0.7298, 1.49618, 1.49618, 40.0
