@@ -3,11 +3,11 @@
 //
 // A pre-pass (k_eval_operands) makes the shifted points once, in the
 // precision's operand format (shift in double, one rounding to float).  A
-// workgroup (4 waves) owns a 128-row x 128-point tile of Z.  The K loop
-// stages 32 coordinates of its points in LDS, shared by the 4 waves, with
-// the next chunk's loads issued before this chunk's MFMAs; each wave streams
-// its own 32 rows of M (two 16-row MFMA tiles) from L2 and accumulates
-// 2 x 8 MFMA tiles.  Precision variants:
+// workgroup (4 waves) owns a 128-row x PT-point tile of Z (PT = 128 or
+// 64).  The K loop stages 32 coordinates of its points in LDS, shared by the
+// 4 waves, with the next chunk's loads issued before this chunk's MFMAs; each
+// wave streams its own 32 rows of M (two 16-row MFMA tiles) from L2 and
+// accumulates 2 x PT / 16 MFMA tiles.  Precision variants:
 //   FP32        v_mfma_f32_16x16x4_f32 on float operands;
 //   split bf16  every float is split into three bf16 terms, hi = bf16(f),
 //               mid = bf16(f - hi), lo = bf16(f - hi - mid), whose sum is f
@@ -53,16 +53,13 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float f)
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 constexpr int KC = 32;                 // coordinates per K chunk
-constexpr int PT = LARGE_POINTS;       // points per workgroup
-constexpr int CT = PT / 16;            // column tiles per wave
-constexpr int SB = PT + 16;            // float staging row stride (bank offset 16)
 constexpr int SK = KC + 8;             // bf16 staging row stride (80 bytes)
 
-template <int FUNC>
+template <int FUNC, int CT>
 __device__ __forceinline__ void fold_rows(const floatx4 (&z)[2][CT], int rt0, int w, int lane,
                                           int dim, const SEVO_GLOBAL float *__restrict__ tab,
-                                          const float (*sZ0)[PT], const SchwefelConst<float> &K,
-                                          float (*sAcc)[PT][4])
+                                          const float (*sZ0)[CT * 16], const SchwefelConst<float> &K,
+                                          float (*sAcc)[CT * 16][4])
 {
     const int kq = lane >> 4, pc = lane & 15;
     const int src = (lane + 16) & 63;
@@ -104,7 +101,7 @@ __device__ __forceinline__ void fold_rows(const floatx4 (&z)[2][CT], int rt0, in
     }
 }
 
-template <int FUNC>
+template <int FUNC, int PT>
 __device__ __forceinline__ void merge_waves(float rec[4], const float (*sAcc)[PT][4], int p)
 {
     AccF a{rec[0], rec[1], rec[2], rec[3]};
@@ -188,10 +185,16 @@ __global__ __launch_bounds__(256) void k_eval_operands(const EvalDesc *__restric
     }
 }
 
-template <bool BF16>
+// PT points per workgroup: 128 (one operand tile) or 64 (half of one; twice
+// the workgroups, half the accumulators, so more workgroups fit a CU and the
+// last round of a grid that does not divide evenly is shorter)
+template <bool BF16, int PT>
 __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__ items, int n_items,
                                                     int total_blocks, Consts K)
 {
+    constexpr int CT = PT / 16;        // column tiles per wave
+    constexpr int SB = PT + 16;        // float staging row stride (bank offset 16)
+    static_assert(PT == 64 || PT == 128, "a workgroup covers one operand tile or half of one");
     __shared__ __attribute__((aligned(16))) float sB[BF16 ? 4 : KC * SB];
     __shared__ __attribute__((aligned(16))) uint16_t sBt[BF16 ? 3 : 1][BF16 ? PT * SK : 8];
     __shared__ float sZ0[4][PT];
@@ -204,6 +207,9 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
     const int local = L - it.block0;
     const int rb = local % RB, pb = local / RB;
     const int p_base = pb * PT;
+    // operand tile of these points and their first column in it
+    const int64_t otile = p_base / LARGE_POINTS;
+    const int ocol = p_base % LARGE_POINTS;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int kq = lane >> 4, pc = lane & 15;
     const int RT = (dim + 15) / 16, KS = (dim + 3) / 4, K32 = (dim + 31) / 32;
@@ -219,19 +225,25 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
 
     if constexpr (BF16) {
         // split operands from k_eval_operands: 128 points x 32 coordinates per
-        // chunk and term array = 512 vectors of 8 bf16, two per thread and
-        // term; the next chunk's vectors and M fragments are loaded before
-        // this chunk's MFMAs
+        // chunk and term array = 512 vectors of 8 bf16 (4 per point), of
+        // which this workgroup's PT points take 4 PT contiguous ones, PT / 64
+        // per thread and term; the next chunk's vectors and M fragments are
+        // loaded before this chunk's MFMAs
         const int64_t kp = large_kpad(dim), np = large_npad(n);
         // global (not flat) loads: a flat load also counts against the LDS
         // counter, so the waits for this chunk's LDS reads would wait for the
         // next chunk's loads as well
         const SEVO_GLOBAL vu32x4 *Bt = gin<vu32x4>(it.opnd);
         const int64_t tstride = np * kp / 8;   // vectors per term array
-        // tiled layout: chunk kk of this point tile is 512 contiguous vectors
-        const int v0 = threadIdx.x, v1 = threadIdx.x + 256;
-        const int64_t g0 = (int64_t)pb * K32 * 512 + v0, g1 = g0 + 256;
-        const int s0 = (v0 >> 2) * SK + (v0 & 3) * 8, s1 = (v1 >> 2) * SK + (v1 & 3) * 8;
+        // tiled layout: chunk kk of the operand tile is 512 contiguous vectors
+        constexpr int NV = PT / 64;
+        const int64_t g0 = otile * K32 * 512 + ocol * 4 + threadIdx.x;
+        int sv[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int v = threadIdx.x + 256 * j;
+            sv[j] = (v >> 2) * SK + (v & 3) * 8;
+        }
         const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
         const int64_t mblock = (int64_t)RT * K32 * 512;   // bf16 per term block of M
         // a[r][t]: term t of row tile r's fragment of chunk kk, as raw words.
@@ -253,17 +265,15 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         };
         vu32x4 a[2][3];
         load_a(0, a);
-        vu32x4 b0[3], b1[3];
+        vu32x4 b[NV][3];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            b0[t] = Bt[t * tstride + g0];
-            b1[t] = Bt[t * tstride + g1];
-        }
+        for (int j = 0; j < NV; ++j)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            *reinterpret_cast<vu32x4 *>(sBt[t] + s0) = b0[t];
-            *reinterpret_cast<vu32x4 *>(sBt[t] + s1) = b1[t];
-        }
+            for (int t = 0; t < 3; ++t) b[j][t] = Bt[t * tstride + g0 + 256 * j];
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) *reinterpret_cast<vu32x4 *>(sBt[t] + sv[j]) = b[j][t];
         __syncthreads();
         // every global load of the prologue is complete here; without this
         // wait the compiler's bookkeeping of the fragments loaded before the
@@ -276,18 +286,27 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
             if (more) {
                 const int64_t d = (int64_t)(kk + 1) * 512;
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    b0[t] = Bt[t * tstride + g0 + d];
-                    b1[t] = Bt[t * tstride + g1 + d];
-                }
+                for (int j = 0; j < NV; ++j)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) b[j][t] = Bt[t * tstride + g0 + d + 256 * j];
                 load_a(kk + 1, na);
             }
+            // the three terms of column tile c + 1 are read from LDS while the
+            // MFMAs of tile c run (double-buffered; the order is pinned below,
+            // since the scheduler otherwise reads each tile into the same
+            // registers just before its MFMAs and waits for every read)
+            bf16x8 bb[2][3];
+            auto read_b = [&](int c, bf16x8 (&d)[3]) {
+                const int off = (c * 16 + pc) * SK + kq * 8;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) d[t] = *reinterpret_cast<const bf16x8 *>(sBt[t] + off);
+            };
+            read_b(0, bb[0]);
+            __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
-                const int off = (c * 16 + pc) * SK + kq * 8;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(sBt[0] + off);
-                const bf16x8 bm = *reinterpret_cast<const bf16x8 *>(sBt[1] + off);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(sBt[2] + off);
+                if (c + 1 < CT) read_b(c + 1, bb[(c + 1) & 1]);
+                const bf16x8 bh = bb[c & 1][0], bm = bb[c & 1][1], bl = bb[c & 1][2];
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
                     const bf16x8 ah = __builtin_bit_cast(bf16x8, a[r][0]);
@@ -302,13 +321,17 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                     z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, z[r][c], 0, 0, 0);
                     z[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, z[r][c], 0, 0, 0);
                 }
+                if (c + 1 < CT) __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);   // LDS reads
+                __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);                 // MFMAs
             }
             __syncthreads();
             if (more) {
 #pragma unroll
+                for (int j = 0; j < NV; ++j)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) *reinterpret_cast<vu32x4 *>(sBt[t] + sv[j]) = b[j][t];
+#pragma unroll
                 for (int t = 0; t < 3; ++t) {
-                    *reinterpret_cast<vu32x4 *>(sBt[t] + s0) = b0[t];
-                    *reinterpret_cast<vu32x4 *>(sBt[t] + s1) = b1[t];
                     a[0][t] = na[0][t];
                     a[1][t] = na[1][t];
                 }
@@ -317,18 +340,22 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         }
     } else {
         // float operands from k_eval_operands: 32 coordinates x 128 points
-        // per chunk = 1024 vectors of 4 floats, four per thread; the next
-        // chunk's vectors and M fragments are loaded before this chunk's
-        // MFMAs (same structure as the split path)
+        // per chunk = 1024 vectors of 4 floats (32 per coordinate row), of
+        // which this workgroup's PT points take PT / 4 of every row, PT / 32
+        // per thread; the next chunk's vectors and M fragments are loaded
+        // before this chunk's MFMAs (same structure as the split path)
         const SEVO_GLOBAL vu32x4 *Bf = gin<vu32x4>(it.opnd);
-        const int64_t g0 = (int64_t)pb * K32 * 1024 + threadIdx.x;
-        // vector v = k (32 vectors per row) and 4 points; LDS row stride SB
-        int sv[4];
+        constexpr int VPR = PT / 4, NV = PT / 32;
+        // vector v of the workgroup = row v / VPR, 4 points at column v % VPR;
+        // LDS row stride SB
+        const int64_t g0 = otile * K32 * 1024 + (threadIdx.x / VPR) * 32 + ocol / 4 + threadIdx.x % VPR;
+        int sv[NV];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NV; ++j) {
             const int v = threadIdx.x + 256 * j;
-            sv[j] = (v >> 5) * SB + (v & 31) * 4;
+            sv[j] = (v / VPR) * SB + (v % VPR) * 4;
         }
+        constexpr int GSTEP = (256 / VPR) * 32;   // global vectors between a thread's rows
         const int64_t m0 = (int64_t)min(rt0, RT - 1) * KS * 64 + lane;
         const int64_t m1 = (int64_t)min(rt0 + 1, RT - 1) * KS * 64 + lane;
         // k-steps past the matrix read the last one (their operand rows are
@@ -344,11 +371,11 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         };
         float a0[KC / 4], a1[KC / 4];
         load_a(0, a0, a1);
-        vu32x4 b[4];
+        vu32x4 b[NV];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = Bf[g0 + 256 * j];
+        for (int j = 0; j < NV; ++j) b[j] = Bf[g0 + GSTEP * j];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
+        for (int j = 0; j < NV; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
         __syncthreads();
         // every global load of the prologue is complete here; without this
         // wait the compiler's bookkeeping of the fragments loaded before the
@@ -361,14 +388,16 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
             if (more) {
                 const int64_t d = (int64_t)(kk + 1) * 1024;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = Bf[g0 + d + 256 * j];
+                for (int j = 0; j < NV; ++j) b[j] = Bf[g0 + d + GSTEP * j];
                 load_a(kk + 1, n0, n1);
             }
             // the points of k-step ks + 1 are read from LDS while the MFMAs
-            // of k-step ks run
+            // of k-step ks run (double-buffered; the order is pinned, as in
+            // the split path: CT / 2 paired reads, then 2 CT MFMAs)
             float bv[2][CT];
 #pragma unroll
             for (int c = 0; c < CT; ++c) bv[0][c] = sB[kq * SB + c * 16 + pc];
+            __builtin_amdgcn_sched_group_barrier(0x100, CT / 2, 0);
 #pragma unroll
             for (int ks = 0; ks < KC / 4; ++ks) {
                 if (ks + 1 < KC / 4) {
@@ -380,11 +409,13 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                     z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv[ks & 1][c], z[0][c], 0, 0, 0);
                     z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv[ks & 1][c], z[1][c], 0, 0, 0);
                 }
+                if (ks + 1 < KC / 4) __builtin_amdgcn_sched_group_barrier(0x100, CT / 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 2 * CT, 0);
             }
             __syncthreads();
             if (more) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
+                for (int j = 0; j < NV; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
 #pragma unroll
                 for (int ks = 0; ks < KC / 4; ++ks) {
                     a0[ks] = n0[ks];
@@ -405,12 +436,12 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         for (int c = 0; c < CT; ++c) sZL[c * 16 + pc] = z[1][c][3];
     __syncthreads();
     switch (it.func) {
-    case ELLIPSOID: fold_rows<ELLIPSOID>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
-    case ROSENBROCK: fold_rows<ROSENBROCK>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
-    case RASTRIGIN: fold_rows<RASTRIGIN>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
-    case SCHWEFEL: fold_rows<SCHWEFEL>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
-    case GRIEWANK: fold_rows<GRIEWANK>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
-    default: fold_rows<ACKLEY>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case ELLIPSOID: fold_rows<ELLIPSOID, CT>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case ROSENBROCK: fold_rows<ROSENBROCK, CT>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case RASTRIGIN: fold_rows<RASTRIGIN, CT>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case SCHWEFEL: fold_rows<SCHWEFEL, CT>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    case GRIEWANK: fold_rows<GRIEWANK, CT>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
+    default: fold_rows<ACKLEY, CT>(z, rt0, w, lane, dim, tab, sZ0, K.kf, sAcc); break;
     }
     __syncthreads();
     if (threadIdx.x < PT) {
@@ -418,9 +449,9 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         if (pg < n) {
             float rec[4] = {sAcc[0][p][0], sAcc[0][p][1], sAcc[0][p][2], sAcc[0][p][3]};
             switch (it.func) {
-            case ACKLEY: merge_waves<ACKLEY>(rec, sAcc, p); break;
-            case GRIEWANK: merge_waves<GRIEWANK>(rec, sAcc, p); break;
-            default: merge_waves<ELLIPSOID>(rec, sAcc, p); break;
+            case ACKLEY: merge_waves<ACKLEY, PT>(rec, sAcc, p); break;
+            case GRIEWANK: merge_waves<GRIEWANK, PT>(rec, sAcc, p); break;
+            default: merge_waves<ELLIPSOID, PT>(rec, sAcc, p); break;
             }
             SEVO_GLOBAL float *out = gout<float>(it.part) + ((int64_t)rb * n + pg) * 8;
             out[0] = rec[0];
@@ -476,15 +507,13 @@ __global__ __launch_bounds__(256) void k_eval_large_combine(const EvalDesc *__re
 }
 
 hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blocks,
-                             bool split_bf16, const Consts &k, hipStream_t s)
+                             bool split_bf16, int points, const Consts &k, hipStream_t s)
 {
     if (total_blocks <= 0) return hipSuccess;
-    if (split_bf16)
-        hipLaunchKernelGGL(k_eval_large<true>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
-                           total_blocks, k);
-    else
-        hipLaunchKernelGGL(k_eval_large<false>, dim3(total_blocks), dim3(256), 0, s, d_items, n_items,
-                           total_blocks, k);
+    if (points != 64 && points != 128) return hipErrorInvalidValue;
+    const auto kern = split_bf16 ? (points == 64 ? k_eval_large<true, 64> : k_eval_large<true, 128>)
+                                 : (points == 64 ? k_eval_large<false, 64> : k_eval_large<false, 128>);
+    hipLaunchKernelGGL(kern, dim3(total_blocks), dim3(256), 0, s, d_items, n_items, total_blocks, k);
     return hipGetLastError();
 }
 

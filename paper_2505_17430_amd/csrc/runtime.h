@@ -84,9 +84,10 @@ hipError_t launch_eval_small(const EvalDesc *d_items, int n_items, int ks, int t
                              bool bf16, const Consts &k, hipStream_t s);
 
 constexpr int LARGE_ROWS = 128;          // rows of z per workgroup (4 waves x 32)
-constexpr int LARGE_POINTS = 128;        // points per workgroup
+constexpr int LARGE_POINTS = 128;        // points per operand tile
+// points: per workgroup, 128 (one operand tile) or 64 (half of one)
 hipError_t launch_eval_large(const EvalDesc *d_items, int n_items, int total_blocks,
-                             bool split_bf16, const Consts &k, hipStream_t s);
+                             bool split_bf16, int points, const Consts &k, hipStream_t s);
 hipError_t launch_eval_large_combine(const EvalDesc *d_items, int n_items, int total_blocks,
                                      const Consts &k, hipStream_t s);
 // GEMM operands of the large-D points, made by a pre-pass: d = x - o
@@ -94,9 +95,10 @@ hipError_t launch_eval_large_combine(const EvalDesc *d_items, int n_items, int t
 // (128-point tile, 32-coordinate chunk) in the order in which the
 // evaluation stages one chunk:
 //   FP32        [npad / 128][kpad / 32][32 k][128 points] floats;
-//   split bf16  hi = bf16(d), lo = bf16(d - hi): the hi array then the lo
-//               array, each [npad / 128][kpad / 32][128 points][32 k].
-// Either way 4 npad kpad bytes.  Workgroups of 64 points x 32 coordinates.
+//   split bf16  hi = bf16(d), mid = bf16(d - hi), lo = bf16(d - hi - mid):
+//               the three arrays one after another, each
+//               [npad / 128][kpad / 32][128 points][32 k].
+// So 4 or 6 npad kpad bytes.  Workgroups of 64 points x 32 coordinates.
 constexpr int OPERAND_POINTS = 64, OPERAND_K = 32;
 __host__ __device__ inline int64_t large_npad(int n) { return ((int64_t)n + LARGE_POINTS - 1) / LARGE_POINTS * LARGE_POINTS; }
 __host__ __device__ inline int64_t large_kpad(int dim) { return ((int64_t)dim + 31) / 32 * 32; }

@@ -158,6 +158,7 @@ struct sevo_ctx {
     int last_slot = -1;
     Consts consts;
     int tiles_per_block = 0;     // SEVO_TILES_PER_BLOCK override; 0 = none
+    int large_points = 64;       // points per D > 120 GEMM workgroup (SEVO_LARGE_POINTS: 64 or 128)
     int tuned_tpb[2][64] = {};   // sevo_tune_evaluate's choice per (float / split-bf16 kernel, k-step
                                  // class); 0 = resident grid
     sevo::Workspace ws;
@@ -497,12 +498,13 @@ int sevo::prepare_eval(sevo_ctx *ctx, std::vector<EvalDesc> items, int precision
         for (auto &d : large) {
             d.rb = (d.dim + LARGE_ROWS - 1) / LARGE_ROWS;
             d.block0 = blocks;
-            d.nblocks = d.rb * ((d.n + LARGE_POINTS - 1) / LARGE_POINTS);
+            d.nblocks = d.rb * ((d.n + ctx->large_points - 1) / ctx->large_points);
             blocks += d.nblocks;
             d.part = part + off;
             off += (size_t)d.rb * d.n * 8;
         }
-        out.push_back({Launch{L_LARGE, nullptr, (int)large.size(), 0, blocks, 0, precision == SEVO_SPLIT_BF16,
+        out.push_back({Launch{L_LARGE, nullptr, (int)large.size(), ctx->large_points, blocks, 0,
+                              precision == SEVO_SPLIT_BF16,
                               false, 0, 0, 0},
                        table_blob(large)});
         // combine: one thread per point, blocks of 256 points
@@ -671,7 +673,7 @@ static hipError_t exec_launch(sevo_ctx *ctx, const sevo::Launch &L, hipStream_t 
     case L_SMALL:
         return launch_eval_small((const EvalDesc *)L.d, L.n, L.ks, L.total, L.grid, L.flag, ctx->consts, s);
     case L_F64: return launch_eval_f64((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
-    case L_LARGE: return launch_eval_large((const EvalDesc *)L.d, L.n, L.total, L.flag, ctx->consts, s);
+    case L_LARGE: return launch_eval_large((const EvalDesc *)L.d, L.n, L.total, L.flag, L.ks, ctx->consts, s);
     case L_COMBINE: return launch_eval_large_combine((const EvalDesc *)L.d, L.n, L.total, ctx->consts, s);
     case L_OPERANDS: return launch_eval_operands((const EvalDesc *)L.d, L.n, L.total, L.flag, s);
     case L_RUN: return exec_run_launch(L, s, fold_seed(ctx->base_seed), ctx->consts);
@@ -753,6 +755,7 @@ int sevo_create(sevo_ctx **out, int32_t hip_device, uint64_t base_seed, uint64_t
     ctx->inst_seed = instance_seed;
     ctx->consts = make_consts();
     if (const char *e = std::getenv("SEVO_TILES_PER_BLOCK")) ctx->tiles_per_block = std::atoi(e);
+    if (const char *e = std::getenv("SEVO_LARGE_POINTS")) ctx->large_points = std::atoi(e) == 128 ? 128 : 64;
     DeviceGuard g(hip_device);
     e = hipGetSymbolAddress((void **)&ctx->scratch, HIP_SYMBOL(scratch));
     if (e != hipSuccess)

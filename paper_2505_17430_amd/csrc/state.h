@@ -41,7 +41,7 @@ enum { L_SMALL = 0, L_F64 = 1, L_LARGE = 2, L_COMBINE = 3, L_RUN = 4, L_CSO = 5,
 struct Launch {
     int kind;
     const void *d;      // device descriptors
-    int n, ks, total, grid;
+    int n, ks, total, grid;   // ks: L_SMALL K steps; L_LARGE points per workgroup
     bool flag;          // L_SMALL, L_LARGE, L_OPERANDS: split bf16; L_RUN: population on chip
     bool wave;          // L_RUN: wave teams
     size_t shm;         // L_RUN: dynamic LDS bytes

@@ -215,6 +215,38 @@ def test_launch_shape_and_autotune_do_not_change_results(ctx, monkeypatch):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", [S.FP32, S.SPLIT_BF16])
+def test_large_d_workgroup_width_does_not_change_results(ctx, monkeypatch, precision):
+    """The D > 120 GEMM gives the same bits with 64 or 128 points per
+    workgroup (one batch of several items, ragged point counts, Rosenbrock's
+    neighbours across row blocks); both agree with the oracle."""
+    groups = [(1, 200, 0, 333), (4, 1000, 1, 130), (5, 129, 2, 64), (3, 300, 3, 257)]
+    errs, items, pts = [], [], []
+    for (f, d, k, n) in groups:
+        X = W.uniform_points(W.group_seed(f, d, k, 12), d, n)
+        pts.append(X)
+        e = torch.zeros(n, device="cuda")
+        errs.append(e)
+        items.append((S.problem(f, d), k, torch.from_numpy(X).cuda(), e))
+    arr = S.Context.prepare_batch(items)
+    got = {}
+    for width in ("64", "128"):
+        monkeypatch.setenv("SEVO_LARGE_POINTS", width)
+        c2 = S.Context(0, W.BASE_SEED, W.INSTANCE_SEED)
+        for e in errs:
+            e.fill_(float("nan"))
+        c2.evaluate_batch(arr, precision=precision)
+        torch.cuda.synchronize()
+        got[width] = [e.cpu().numpy().copy() for e in errs]
+        c2.close()
+        say("  points per workgroup", width)
+    monkeypatch.delenv("SEVO_LARGE_POINTS")
+    for (f, d, k, n), X, a, b in zip(groups, pts, got["64"], got["128"]):
+        assert np.array_equal(a, b), (f, d, n)
+        o, M = O.instance(f, d, k, ISEED)
+        check_f32(a, f, o, M, X, O.errors_soa_f32(f, o, M, X), f"width f{f} D{d} n{n}")
+
+
 def test_invalid_arguments(ctx):
     x = torch.zeros((10, 4), device="cuda")
     e = torch.zeros(4, device="cuda")
