@@ -359,8 +359,9 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         const int64_t m0 = (int64_t)min(rt0, RT - 1) * KS * 64 + lane;
         const int64_t m1 = (int64_t)min(rt0 + 1, RT - 1) * KS * 64 + lane;
         // k-steps past the matrix read the last one (their operand rows are
-        // zero); row tiles past the matrix read the last real one, as in the
-        // split path (the fold discards their rows)
+        // zero, and the last chunk skips them); row tiles past the matrix
+        // read the last real one, as in the split path (the fold discards
+        // their rows)
         auto load_a = [&](int kk, float (&a0)[KC / 4], float (&a1)[KC / 4]) {
 #pragma unroll
             for (int ks = 0; ks < KC / 4; ++ks) {
@@ -382,15 +383,14 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         // loop makes each iteration wait for all loads in flight, the next
         // chunk's prefetch included (vmcnt 0; expcnt and lgkmcnt unconstrained)
         __builtin_amdgcn_s_waitcnt(0x0F70);
-        for (int kk = 0; kk < K32; ++kk) {
-            const bool more = kk + 1 < K32;
+        // every chunk but the last: all eight k-steps, the next chunk loaded
+        // meanwhile
+        for (int kk = 0; kk + 1 < K32; ++kk) {
             float n0[KC / 4], n1[KC / 4];
-            if (more) {
-                const int64_t d = (int64_t)(kk + 1) * 1024;
+            const int64_t d = (int64_t)(kk + 1) * 1024;
 #pragma unroll
-                for (int j = 0; j < NV; ++j) b[j] = Bf[g0 + d + GSTEP * j];
-                load_a(kk + 1, n0, n1);
-            }
+            for (int j = 0; j < NV; ++j) b[j] = Bf[g0 + d + GSTEP * j];
+            load_a(kk + 1, n0, n1);
             // the points of k-step ks + 1 are read from LDS while the MFMAs
             // of k-step ks run (double-buffered; the order is pinned, as in
             // the split path: CT / 2 paired reads, then 2 CT MFMAs)
@@ -413,16 +413,28 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
                 __builtin_amdgcn_sched_group_barrier(0x008, 2 * CT, 0);
             }
             __syncthreads();
-            if (more) {
 #pragma unroll
-                for (int j = 0; j < NV; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
+            for (int j = 0; j < NV; ++j) *reinterpret_cast<vu32x4 *>(sB + sv[j]) = b[j];
 #pragma unroll
-                for (int ks = 0; ks < KC / 4; ++ks) {
-                    a0[ks] = n0[ks];
-                    a1[ks] = n1[ks];
-                }
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                a0[ks] = n0[ks];
+                a1[ks] = n1[ks];
             }
             __syncthreads();
+        }
+        // the last chunk (in LDS now): only its k-steps inside the matrix;
+        // the operand rows past dim are zero, so the others add nothing
+        const int nks = KS - (K32 - 1) * (KC / 4);
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            if (ks < nks) {
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const float bvc = sB[(ks * 4 + kq) * SB + c * 16 + pc];
+                    z[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bvc, z[0][c], 0, 0, 0);
+                    z[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bvc, z[1][c], 0, 0, 0);
+                }
+            }
         }
     }
 
