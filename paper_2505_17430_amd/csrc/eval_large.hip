@@ -53,7 +53,6 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float f)
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 constexpr int KC = 32;                 // coordinates per K chunk
-constexpr int SK = KC + 8;             // bf16 staging row stride (80 bytes)
 
 template <int FUNC, int CT>
 __device__ __forceinline__ void fold_rows(const floatx4 (&z)[2][CT], int rt0, int w, int lane,
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
     constexpr int SB = PT + 16;        // float staging row stride (bank offset 16)
     static_assert(PT == 64 || PT == 128, "a workgroup covers one operand tile or half of one");
     __shared__ __attribute__((aligned(16))) float sB[BF16 ? 4 : KC * SB];
-    __shared__ __attribute__((aligned(16))) uint16_t sBt[BF16 ? 3 : 1][BF16 ? PT * SK : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sBt[BF16 ? 3 : 1][BF16 ? PT * KC : 8];
     __shared__ float sZ0[4][PT];
     __shared__ float sZL[PT];
     __shared__ float sAcc[4][PT][4];
@@ -235,15 +234,19 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
         // next chunk's loads as well
         const SEVO_GLOBAL vu32x4 *Bt = gin<vu32x4>(it.opnd);
         const int64_t tstride = np * kp / 8;   // vectors per term array
-        // tiled layout: chunk kk of the operand tile is 512 contiguous vectors
+        // tiled layout: chunk kk of the operand tile is 512 contiguous vectors,
+        // point-major (vector 4 p + q = coordinates 8 q .. 8 q + 7 of point p).
+        // In LDS the vectors are in the order the MFMA lanes read them:
+        // slot 64 c + 16 q + i holds vector q of point 16 c + i, so a wave's
+        // reads of one column tile, and its stores, are 1 KB contiguous (no
+        // bank conflicts); its global loads still cover 1 KB contiguous.
+        // Slot v + 256 holds the vector 256 past slot v's.
         constexpr int NV = PT / 64;
-        const int64_t g0 = otile * K32 * 512 + ocol * 4 + threadIdx.x;
+        const int t0 = threadIdx.x;
+        const int64_t g0 = otile * K32 * 512 + ocol * 4 + ((t0 >> 6) * 16 + (t0 & 15)) * 4 + ((t0 >> 4) & 3);
         int sv[NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const int v = threadIdx.x + 256 * j;
-            sv[j] = (v >> 2) * SK + (v & 3) * 8;
-        }
+        for (int j = 0; j < NV; ++j) sv[j] = (t0 + 256 * j) * 8;
         const SEVO_GLOBAL uint16_t *Mh = gin<uint16_t>(it.Mbf);
         const int64_t mblock = (int64_t)RT * K32 * 512;   // bf16 per term block of M
         // a[r][t]: term t of row tile r's fragment of chunk kk, as raw words.
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(256) void k_eval_large(const EvalDesc *__restrict__
             // registers just before its MFMAs and waits for every read)
             bf16x8 bb[2][3];
             auto read_b = [&](int c, bf16x8 (&d)[3]) {
-                const int off = (c * 16 + pc) * SK + kq * 8;
+                const int off = (c * 64 + lane) * 8;
 #pragma unroll
                 for (int t = 0; t < 3; ++t) d[t] = *reinterpret_cast<const bf16x8 *>(sBt[t] + off);
             };
