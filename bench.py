@@ -222,7 +222,12 @@ def main():
 
     def timed(prec, reps, steps, warmup, tune=True):
         """Time `steps` steps of the sweep in one precision; returns
-        (ms per step, mean D=100 launch ms, tuned launch shapes)."""
+        (ms per step, mean D=100 launch ms, tuned launch shapes, ms per step
+        of the eager calls).  A step launches one prepared plan
+        (sevo_plan_evaluate: descriptor tables resident, launch shapes fixed,
+        no host work per call) per dimension class and replica; the same
+        sweep through one sevo_evaluate_batch call per class is timed after
+        it.  Both do all the work of every step."""
         # launch shapes chosen by the library's autotuner on the first replica
         # (setup, outside the timed region; the choice does not change results)
         tuned = {}
@@ -230,40 +235,54 @@ def main():
             for d in W.C2_DIMS:
                 tuned.update(ctx.tune_evaluate(reps[0][d][1], precision=prec, stream=stream))
 
-        def step(rep, ev=None):
+        plans = [{d: ctx.plan_evaluate(rep[d][1], precision=prec) for d in W.C2_DIMS} for rep in reps]
+
+        def step(i, ev=None, eager=False):
+            rep, pl = reps[i % len(reps)], plans[i % len(reps)]
             for d in W.C2_DIMS:
                 if ev is not None and d == 100:
                     ev[0].record(stream)
-                ctx.evaluate_batch(rep[d][1], precision=prec, stream=stream)
+                if eager:
+                    ctx.evaluate_batch(rep[d][1], precision=prec, stream=stream)
+                else:
+                    pl[d].launch(stream)
                 if ev is not None and d == 100:
                     ev[1].record(stream)
 
-        for w in range(warmup):
-            step(reps[w % len(reps)])
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)]
-        t_start = torch.cuda.Event(enable_timing=True)
-        t_end = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t_start.record(stream)
-        for s in range(steps):
-            step(reps[s % len(reps)], evs[s])
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        ctx.sync(stream)
+        def run(eager):
+            for w in range(warmup):
+                step(w, eager=eager)
+            torch.cuda.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+            t_start = torch.cuda.Event(enable_timing=True)
+            t_end = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t_start.record(stream)
+            for s in range(steps):
+                step(s, evs[s], eager)
+            t_end.record(stream)
+            torch.cuda.synchronize()
+            ctx.sync(stream)
+            return (t_start.elapsed_time(t_end) / steps,
+                    float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])))
+
+        ms, d100 = run(False)
+        ms_eager, _ = run(True)
         # leave replica 0 holding this precision's results (for the accuracy sample)
-        step(reps[0])
+        step(0)
         torch.cuda.synchronize()
-        return (t_start.elapsed_time(t_end) / steps,
-                float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])), tuned)
+        for pl in plans:
+            for p in pl.values():
+                p.close()
+        return ms, d100, tuned, ms_eager
 
     def keep0(reps):
         return [t for d in W.C2_DIMS for t in reps[0][d][2]]
 
     n100 = sum(g[3] for g in by_dim[100])
     flops100 = 2.0 * 100 * 100 * n100
-    ms_step, d100_ms, tuned = timed(prec, reps, a.steps, a.warmup)
+    ms_step, d100_ms, tuned, ms_eager = timed(prec, reps, a.steps, a.warmup)
     value = n_evals / (ms_step / 1e3)
     accuracy = {}
     if not a.no_cpu:
@@ -274,12 +293,14 @@ def main():
         # evaluation tolerance in the parity tests)
         other = S.SPLIT_BF16 if prec == S.FP32 else S.FP32
         oname = "split_bf16" if other == S.SPLIT_BF16 else "fp32"
-        o_ms, o_d100, o_tuned = timed(other, reps, a.steps, a.warmup)
+        o_ms, o_d100, o_tuned, o_eager = timed(other, reps, a.steps, a.warmup)
         if not a.no_cpu:
             accuracy[oname] = cpu_accuracy(keep0(reps), oname)
-        for name, pr, ms_, d_ in ((a.precision, prec, ms_step, d100_ms), (oname, other, o_ms, o_d100)):
+        for name, pr, ms_, d_, me_ in ((a.precision, prec, ms_step, d100_ms, ms_eager),
+                                       (oname, other, o_ms, o_d100, o_eager)):
             legs["split_bf16" if name == "bf16" else name] = {
                 "ms_per_step": round(ms_, 4), "evals_per_s": round(n_evals / (ms_ / 1e3), 1),
+                "eager_ms_per_step": round(me_, 4),
                 "d100_kernel_ms": round(d_, 4),
                 "d100_tflops_fp32_equiv": round(flops100 / (d_ / 1e3) / 1e12, 3)}
     fp64, c1, speedup = None, None, None
@@ -289,7 +310,7 @@ def main():
         # replica (its working set alone exceeds the Infinity Cache)
         reps64 = replicas(torch.float64, 1)
         f64_steps = max(1, min(a.steps, 10))
-        ms64, d100_64, _ = timed(S.FP64, reps64, f64_steps, 1, tune=False)
+        ms64, d100_64, _, ms64_eager = timed(S.FP64, reps64, f64_steps, 1, tune=False)
         # the same in one launch per run: each run's 100-point population of each
         # (function, D, instance) evaluated by its own sevo_evaluate call
         singles = [(S.problem(f, d), k, x[:, r * W.C2_POINTS_PER_RUN:(r + 1) * W.C2_POINTS_PER_RUN],
@@ -307,8 +328,9 @@ def main():
         ms_per_run = p0.elapsed_time(p1)
         del reps64, singles
         fp64 = {"batched": {"ms_per_step": round(ms64, 4), "evals_per_s": round(n_evals / (ms64 / 1e3), 1),
+                            "eager_ms_per_step": round(ms64_eager, 4),
                             "d100_kernel_ms": round(d100_64, 4), "steps": f64_steps,
-                            "path": "sevo_evaluate_batch, precision FP64 (k_eval_f64), the same calls and "
+                            "path": "precision FP64 (k_eval_f64), the same plans, calls and "
                                     "event timing as the single-precision legs"},
                 "one_run_per_launch": {"ms_per_step": round(ms_per_run, 3),
                                        "evals_per_s": round(n_evals / (ms_per_run / 1e3), 1),
@@ -350,6 +372,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms_step, 4),
+        "eager_ms_per_step": round(ms_eager, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None if speedup is None else round(speedup, 3),
@@ -366,6 +389,8 @@ def main():
                    "evals_per_step": n_evals, "input_bytes_per_step": bytes_in,
                    "replicas": a.replicas, "precision": a.precision,
                    "tiles_per_workgroup": {str(k): v for k, v in sorted(tuned.items())} or "resident grid",
+                   "launch": "per step one prepared plan (sevo_plan_evaluate) per dimension class; "
+                             "eager_ms_per_step: one sevo_evaluate_batch call per class instead",
                    "tolerance": "|de| <= max(1e-6, 1e-5 e) vs the FP64 oracle for ellipsoid, rastrigin, "
                                 "schwefel, griewank, ackley; rosenbrock + 4 eps32 |x - o|_2 |grad_z e|_1 "
                                 "(asserted by the parity tests; measured below under accuracy)"},
