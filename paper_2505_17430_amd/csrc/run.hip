@@ -122,7 +122,11 @@ static size_t onchip_limit(int ks, bool wave, int fam)
         const void *k = (const void *)run_table(fam, ks, true, wave);
         hipFuncAttributes fa;
         const size_t total = std::min((size_t)maxblk, CAP);
-        if (k && hipFuncGetAttributes(&fa, k) == hipSuccess && total > fa.sharedSizeBytes) {
+        // an on-chip variant that spills registers to scratch (at the largest
+        // k-step counts of some families) is never used: its runs take the
+        // workspace variant, which does not spill
+        if (k && hipFuncGetAttributes(&fa, k) == hipSuccess && fa.localSizeBytes == 0 &&
+            total > fa.sharedSizeBytes) {
             const size_t want = total - fa.sharedSizeBytes;
             if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
                 lim = want;
